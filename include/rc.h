@@ -1,0 +1,227 @@
+/*
+ * rc.h - real-time FMCW SAR back-projection on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of librc.so.  The library forms SAR images from FMCW radar frames with
+ * the optimised back-projection of Hoffmann et al., "Implementation of
+ * Real-Time Automotive SAR Imaging" (arXiv 2306.09784), Alg. 2, and runs a
+ * cell-averaging CFAR detector on each image.  Per frame it executes, on one
+ * HIP stream:
+ *
+ *   1. range compression: windowed, zero-padded DFT of every chirp/channel
+ *      beat signal, cropped to the kept bins (the equidistant beat spectrum s
+ *      that Alg. 1 and Alg. 2 interpolate, Sec. III-C);
+ *   2. per-frame tables: the per-pixel Doppler shift from the average
+ *      velocity (Sec. III-D);
+ *   3. back-projection (Alg. 2): per pixel, chirp and channel the two-way
+ *      path d_hyp, index f_ind = a1 d_hyp + f_doppler(p), phase
+ *      exp(a2 d_hyp), linear interpolation of s at f_ind, weight w_sar[m]
+ *      (Sec. III-B) and the coherent sum;
+ *   4. 2-D CA-CFAR on |P|^2 over the pixel lattice (a detection stage layered
+ *      on the image; not part of the paper) and ordered compaction of the
+ *      detections.
+ *
+ * Conventions
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  Complex numbers are interleaved
+ *     float pairs (re, im), i.e. complex64.
+ *   - Every function returns an rc_status.  No exception crosses the ABI.  On
+ *     an error the thread-local message of rc_last_error() describes it.
+ *   - A plan is used by one host thread at a time.  Streams are hipStream_t
+ *     passed as void*; NULL means the default stream.
+ *   - Distances are metres, frequencies Hz, times seconds.  Geometry is planar
+ *     (x, y): the paper's 2-D distances.
+ */
+#ifndef RC_H_
+#define RC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RC_ABI_VERSION 1
+
+typedef enum rc_status {
+  RC_OK = 0,
+  RC_EINVAL = 1,     /* bad argument or descriptor; nothing was launched          */
+  RC_ENOMEM = 2,     /* device or pinned memory exhausted, or over the HBM budget */
+  RC_ETRUNC = 3,     /* output buffer too small; *n_out holds the needed count    */
+  RC_EHIP = 4,       /* a HIP runtime call failed; see rc_last_error()            */
+  RC_ENOTREADY = 5,  /* no free frame slot / frame still in flight                */
+  RC_ENOTFOUND = 6   /* unknown frame id                                          */
+} rc_status;
+
+typedef enum rc_window_kind {
+  RC_WIN_RECT = 0,
+  RC_WIN_HANN = 1,   /* symmetric Hann, 0.5 - 0.5 cos(2 pi t / (n - 1))           */
+  RC_WIN_KAISER = 2  /* I0(beta sqrt(1 - (2t/(n-1) - 1)^2)) / I0(beta)            */
+} rc_window_kind;
+
+typedef enum rc_precision {
+  /* Alg. 2 in single precision, as the paper runs it (Sec. III-A). */
+  RC_PREC_FP32 = 0,
+  /* Single precision with the phase split into a per-pixel reference path
+   * (evaluated in double) plus a small single-precision difference; keeps the
+   * carrier phase accurate to ~1e-5 of a turn. */
+  RC_PREC_FP32_SPLIT = 1
+} rc_precision;
+
+typedef enum rc_input_kind {
+  RC_INPUT_RAW = 0,      /* data = beat signal complex64 [n_chirps][n_channels][n_samples] */
+  RC_INPUT_SPECTRUM = 1  /* data = beat spectrum complex64 [n_chirps][n_channels][n_bins]  */
+} rc_input_kind;
+
+/* Radar constants (Tab. I of the paper for its sensor). */
+typedef struct rc_radar {
+  double f0;         /* carrier frequency, Hz (76.6e9)              */
+  double bandwidth;  /* RF bandwidth B, Hz (931e6)                  */
+  double t_chirp;    /* chirp duration T_P, s (102.4e-6)            */
+  double c;          /* propagation speed, m/s; 0 -> 299792458      */
+} rc_radar;
+
+/* Plan descriptor: limits size the per-frame slots allocated at creation. */
+typedef struct rc_plan_desc {
+  int32_t abi_version;          /* must be RC_ABI_VERSION                         */
+  rc_radar radar;
+  int32_t n_samples_max;        /* fast-time samples per chirp                    */
+  int32_t n_fft_max;            /* zero-padded DFT length, power of two <= 4096   */
+  int32_t n_bins_max;           /* kept spectrum bins                             */
+  int32_t n_chirps_max;
+  int32_t n_channels_max;
+  int64_t n_pix_max;
+  int32_t max_frames_in_flight; /* frame slots                                    */
+  int32_t max_detections;       /* detection capacity per frame                   */
+  rc_window_kind range_window;  double range_kaiser_beta;
+  rc_window_kind sar_window;    double sar_kaiser_beta;   /* w_sar over chirps   */
+  rc_precision precision;
+  int32_t cfar_guard;           /* guard cells each side (2)                      */
+  int32_t cfar_train;           /* training cells each side beyond guard (8)      */
+  double cfar_pfa;              /* design false-alarm probability (1e-4)          */
+  double cfar_margin_rel;       /* cells with |power - thr| <= margin * thr are
+                                   flagged RC_DET_NEAR_THRESHOLD                   */
+  int64_t hbm_budget_bytes;     /* 0 = unlimited                                  */
+  int32_t stage_timing;         /* nonzero: bracket every stage with timing events
+                                   (read with rc_stage_times)                      */
+} rc_plan_desc;
+
+/* One radar frame (one synthetic aperture -> one image + detection list).
+ * The caller owns every buffer and keeps it alive until the frame completes
+ * (rc_poll() == RC_OK or rc_detections() returned). */
+typedef struct rc_frame {
+  int64_t frame_id;             /* caller-chosen, unique among frames in flight   */
+  int32_t sensor_id;
+  int32_t n_samples;            /* fast-time samples per chirp (RAW)              */
+  int32_t n_fft;                /* DFT length, power of two >= n_samples (RAW)    */
+  int32_t n_bins;               /* spectrum bins kept and interpolated            */
+  int32_t n_chirps;             /* chirps m (per-TX cycles for TDM-MIMO)          */
+  int32_t n_channels;           /* channels ch per chirp                          */
+  double fs;                    /* IQ sample rate, Hz                             */
+  rc_input_kind input_kind;
+  const void* data;             /* device, see rc_input_kind                      */
+  const float* q_tx;            /* host [n_chirps][n_channels][2] TX positions   */
+  const float* q_rx;            /* host [n_chirps][n_channels][2] RX positions   */
+  const float* vel;             /* host [n_chirps][2] vehicle velocity            */
+  const float* pixels;          /* device [n_rows * n_cols][2] pixel positions p,
+                                   row-major lattice (Cartesian or polar grid)    */
+  int32_t n_rows;
+  int32_t n_cols;
+  void* image_out;              /* device complex64 [n_rows * n_cols] or NULL     */
+  float* doppler_out;           /* device float [n_rows * n_cols] (bins) or NULL  */
+  void* spectrum_out;           /* device complex64 [n_chirps][n_channels][n_bins]
+                                   beat spectrum before w_sar, or NULL            */
+} rc_frame;
+
+#define RC_DET_NEAR_THRESHOLD 1u
+
+typedef struct rc_detection {
+  int32_t pixel;                /* flat lattice index row * n_cols + col          */
+  float power;                  /* |P|^2                                          */
+  float threshold;              /* alpha * mean(training cells)                   */
+  uint32_t flags;               /* RC_DET_*                                       */
+} rc_detection;
+
+/* Create a plan.  Validates the descriptor (RC_EINVAL), sizes every frame slot
+ * from its limits and allocates device and pinned host memory for all slots
+ * up front (RC_ENOMEM if the total exceeds hbm_budget_bytes or an allocation
+ * fails).  *out receives the plan; the caller destroys it with
+ * rc_plan_destroy().  Uses the current HIP device. */
+rc_status rc_plan_create(const rc_plan_desc* desc, void** out);
+
+/* Bytes of device memory one frame slot of this descriptor needs. */
+rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes);
+
+/* Enqueue n_frames frames on stream (Alg. 2 pipeline, steps 1-4 above).
+ * Each frame takes a free slot.  Geometry is copied from the host arrays
+ * before the call returns (through pinned staging), so they may be reused
+ * at once; device inputs must stay valid until the frame completes.
+ * Returns RC_ENOTREADY without enqueuing anything when fewer than n_frames
+ * slots are free, RC_EINVAL on a frame outside the plan's limits or with
+ * inconsistent sizes.  Kernel contributions whose interpolation index lies
+ * outside [0, n_bins - 1] are zero, not an error. */
+rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
+                           void* stream);
+
+/* RC_OK if the frame's work is complete, RC_ENOTREADY if not, RC_ENOTFOUND. */
+rc_status rc_poll(void* plan, int64_t frame_id);
+
+/* Blocks until the frame completes, then copies its detections, in ascending
+ * pixel order, to dst (host).  *n_out = number of detections.  If more than
+ * cap exist, the first cap are copied and RC_ETRUNC is returned; if more than
+ * the plan's max_detections exist, RC_ETRUNC is returned with *n_out = the
+ * true count and max_detections entries are available. */
+rc_status rc_detections(void* plan, int64_t frame_id, rc_detection* dst,
+                        int64_t cap, int64_t* n_out);
+
+/* Copies the frame's complex64 image (n_rows * n_cols) to dst (device) on
+ * stream, after the frame's work.  RC_ETRUNC if cap_pixels is too small. */
+rc_status rc_image(void* plan, int64_t frame_id, void* dst, int64_t cap_pixels,
+                   void* stream);
+
+/* Blocks until the frame completes; ms4 (host, float[4]) receives the device
+ * time in milliseconds of range compression, the per-frame tables,
+ * back-projection and detection (CFAR + compaction), measured with HIP events
+ * recorded on the frame's stream around each stage.  RC_EINVAL if the plan
+ * was created with stage_timing = 0. */
+rc_status rc_stage_times(void* plan, int64_t frame_id, float* ms4);
+
+/* Waits for the frame and returns its slot to the free pool. */
+rc_status rc_frame_release(void* plan, int64_t frame_id);
+
+/* Synchronises outstanding work and frees every resource of the plan. */
+rc_status rc_plan_destroy(void* plan);
+
+/* Thread-local description of the last error ("" if none). */
+const char* rc_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Reconstruction grids (host functions, no GPU work).
+ * ------------------------------------------------------------------------- */
+
+/* Cartesian lattice (Sec. II reference grid): pixel (iy, ix) at
+ * (x0 + ix dx, y0 + iy dy), row-major with y slow, written to xy (host,
+ * float [ny * nx][2]); coordinates are evaluated in double, rounded once. */
+rc_status rc_grid_cartesian(double x0, double dx, int32_t nx, double y0, double dy,
+                            int32_t ny, float* xy);
+
+/* Polar lattice parameters (Sec. III-E): the grid originates at the
+ * synthetic-aperture centre (ox, oy); range step c / (2 B) / factor and
+ * azimuth step lam / (2 L) / factor (L = aperture length, lam = c / f0);
+ * theta is measured from +y towards +x; the lattice spans the range and
+ * angle extent of the box [x0, x1] x [y0, y1] (which must lie at y > oy).
+ * out6 receives {r0, dr, th0, dth, nr, nth}. */
+rc_status rc_grid_polar_params(const rc_radar* radar, double x0, double x1, double y0,
+                               double y1, double ox, double oy, double aperture_len,
+                               double factor, double* out6);
+
+/* Polar lattice points (ith, ir) -> (ox + r sin th, oy + r cos th) with
+ * r = r0 + ir dr, th = th0 + ith dth, row-major with theta slow, written to
+ * xy (host, float [nth * nr][2]). */
+rc_status rc_grid_polar(double ox, double oy, double r0, double dr, int32_t nr,
+                        double th0, double dth, int32_t nth, float* xy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RC_H_ */

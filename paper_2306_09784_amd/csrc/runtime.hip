@@ -1,0 +1,621 @@
+// C-ABI runtime of librc.so: plans, frame slots, host-side geometry
+// preparation and the stream-ordered launch sequence of the pipeline
+//   range compression -> Doppler table -> back-projection (Alg. 2) -> CA-CFAR
+// described in rc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rc.h"
+#include "rc_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+rc_status fail(rc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define RC_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(RC_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                               \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kDetPrefix = 1024;  // detections copied back asynchronously per frame
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+
+double bessel_i0(double x) {
+  // power series sum_k ((x/2)^k / k!)^2, converged to double precision
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+void make_window(rc_window_kind kind, double beta, int n, float* out) {
+  for (int t = 0; t < n; ++t) {
+    double w = 1.0;
+    if (n > 1 && kind == RC_WIN_HANN) {
+      w = 0.5 - 0.5 * std::cos(2.0 * kPi * t / (n - 1));
+    } else if (n > 1 && kind == RC_WIN_KAISER) {
+      const double u = 2.0 * t / (n - 1) - 1.0;
+      w = bessel_i0(beta * std::sqrt(std::max(0.0, 1.0 - u * u))) / bessel_i0(beta);
+    }
+    out[t] = (float)w;
+  }
+}
+
+struct Slot {
+  // device
+  float4* pairs = nullptr;
+  float4* rowgeo = nullptr;   // followed by w_sar[n_chirps_max], w_range[n_samples_max]
+  float* fd = nullptr;
+  float2* image = nullptr;
+  unsigned long long* mask = nullptr;
+  rc_detection* det_cell = nullptr;
+  rc_detection* det_out = nullptr;
+  int64_t* det_count = nullptr;
+  // pinned host
+  float* staging = nullptr;
+  int64_t* h_count = nullptr;
+  rc_detection* h_det = nullptr;
+  hipEvent_t done = nullptr;
+  hipEvent_t stage_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // state
+  bool busy = false;
+  int64_t frame_id = -1;
+  int32_t n_rows = 0, n_cols = 0;
+  float2* image_used = nullptr;
+};
+
+struct Plan {
+  rc_plan_desc d;
+  int device = 0;
+  float2* twiddle = nullptr;
+  int tw_log2 = 0;
+  size_t geo_floats = 0;  // floats of the staging/rowgeo region
+  std::vector<Slot> slots;
+};
+
+struct SlotSizes {
+  size_t pairs, geo, fd, image, mask, det_cell, det_out;
+  size_t total() const { return pairs + geo + fd + image + mask + det_cell + det_out + 64; }
+};
+
+size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+SlotSizes slot_sizes(const rc_plan_desc& d) {
+  SlotSizes s;
+  const size_t rows = (size_t)d.n_chirps_max * d.n_channels_max;
+  s.pairs = round_up(rows * d.n_bins_max * sizeof(float4));
+  s.geo = round_up((rows * 4 + d.n_chirps_max + d.n_samples_max) * sizeof(float));
+  s.fd = round_up((size_t)d.n_pix_max * sizeof(float));
+  s.image = round_up((size_t)d.n_pix_max * sizeof(float2));
+  s.mask = round_up((size_t)d.n_pix_max * sizeof(unsigned long long));
+  s.det_cell = round_up((size_t)d.n_pix_max * sizeof(rc_detection));
+  s.det_out = round_up((size_t)d.max_detections * sizeof(rc_detection));
+  return s;
+}
+
+rc_status validate_desc(const rc_plan_desc* d) {
+  if (!d) return fail(RC_EINVAL, "desc is NULL");
+  if (d->abi_version != RC_ABI_VERSION)
+    return fail(RC_EINVAL, "abi_version %d != %d", d->abi_version, RC_ABI_VERSION);
+  if (!(d->radar.f0 > 0) || !(d->radar.bandwidth > 0) || !(d->radar.t_chirp > 0) ||
+      d->radar.c < 0)
+    return fail(RC_EINVAL, "radar constants must be positive");
+  if (d->n_samples_max < 1 || !is_pow2(d->n_fft_max) || d->n_fft_max < 4 || d->n_fft_max > 4096 ||
+      d->n_samples_max > d->n_fft_max)
+    return fail(RC_EINVAL, "need 1 <= n_samples_max <= n_fft_max, n_fft_max a power of two in [4, 4096]");
+  if (d->n_bins_max < 2 || d->n_bins_max > d->n_fft_max)
+    return fail(RC_EINVAL, "need 2 <= n_bins_max <= n_fft_max");
+  if (d->n_chirps_max < 1 || d->n_channels_max < 1 || d->n_pix_max < 1 ||
+      d->n_pix_max > 0x7fffffffLL || (int64_t)d->n_chirps_max * d->n_channels_max >= (1LL << 31))
+    return fail(RC_EINVAL, "chirp/channel/pixel limits out of range");
+  if (d->max_frames_in_flight < 1 || d->max_frames_in_flight > 1024)
+    return fail(RC_EINVAL, "max_frames_in_flight must be in [1, 1024]");
+  if (d->max_detections < 1) return fail(RC_EINVAL, "max_detections must be >= 1");
+  if (d->cfar_guard < 0 || d->cfar_train < 1 || d->cfar_guard + d->cfar_train > 16)
+    return fail(RC_EINVAL, "need guard >= 0, train >= 1, guard + train <= 16");
+  if (!(d->cfar_pfa > 0 && d->cfar_pfa < 1)) return fail(RC_EINVAL, "cfar_pfa must be in (0, 1)");
+  if (d->cfar_margin_rel < 0) return fail(RC_EINVAL, "cfar_margin_rel must be >= 0");
+  if (d->precision != RC_PREC_FP32)
+    return fail(RC_EINVAL, "precision %d is not available in this build", (int)d->precision);
+  for (rc_window_kind k : {d->range_window, d->sar_window})
+    if (k != RC_WIN_RECT && k != RC_WIN_HANN && k != RC_WIN_KAISER)
+      return fail(RC_EINVAL, "unknown window kind %d", (int)k);
+  return RC_OK;
+}
+
+void free_slot(Slot& s) {
+  if (s.pairs) (void)hipFree(s.pairs);
+  if (s.staging) (void)hipHostFree(s.staging);
+  if (s.h_count) (void)hipHostFree(s.h_count);
+  if (s.done) (void)hipEventDestroy(s.done);
+  for (hipEvent_t& e : s.stage_ev)
+    if (e) (void)hipEventDestroy(e);
+  s = Slot();
+}
+
+void free_plan(Plan* p) {
+  if (!p) return;
+  for (Slot& s : p->slots) free_slot(s);
+  if (p->twiddle) (void)hipFree(p->twiddle);
+  delete p;
+}
+
+Slot* find_slot(Plan* p, int64_t id) {
+  for (Slot& s : p->slots)
+    if (s.busy && s.frame_id == id) return &s;
+  return nullptr;
+}
+
+rc_status validate_frame(const Plan* p, const rc_frame& f) {
+  const rc_plan_desc& d = p->d;
+  if (f.n_chirps < 1 || f.n_chirps > d.n_chirps_max)
+    return fail(RC_EINVAL, "frame %lld: n_chirps %d outside [1, %d]", (long long)f.frame_id, f.n_chirps, d.n_chirps_max);
+  if (f.n_channels < 1 || f.n_channels > d.n_channels_max)
+    return fail(RC_EINVAL, "frame %lld: n_channels %d outside [1, %d]", (long long)f.frame_id, f.n_channels, d.n_channels_max);
+  if (f.n_bins < 2 || f.n_bins > d.n_bins_max)
+    return fail(RC_EINVAL, "frame %lld: n_bins %d outside [2, %d]", (long long)f.frame_id, f.n_bins, d.n_bins_max);
+  if (f.n_rows < 1 || f.n_cols < 1 || (int64_t)f.n_rows * f.n_cols > d.n_pix_max)
+    return fail(RC_EINVAL, "frame %lld: lattice %d x %d outside n_pix_max %lld", (long long)f.frame_id, f.n_rows, f.n_cols, (long long)d.n_pix_max);
+  if (f.n_rows > 65535 * 16)
+    return fail(RC_EINVAL, "frame %lld: n_rows %d too large", (long long)f.frame_id, f.n_rows);
+  if (!(f.fs > 0)) return fail(RC_EINVAL, "frame %lld: fs must be positive", (long long)f.frame_id);
+  if (!f.data || !f.q_tx || !f.q_rx || !f.vel || !f.pixels)
+    return fail(RC_EINVAL, "frame %lld: data, q_tx, q_rx, vel and pixels are required", (long long)f.frame_id);
+  if (f.input_kind == RC_INPUT_RAW) {
+    if (f.n_samples < 1 || f.n_samples > d.n_samples_max)
+      return fail(RC_EINVAL, "frame %lld: n_samples %d outside [1, %d]", (long long)f.frame_id, f.n_samples, d.n_samples_max);
+    if (!is_pow2(f.n_fft) || f.n_fft < 4 || f.n_fft > d.n_fft_max || f.n_fft < f.n_samples)
+      return fail(RC_EINVAL, "frame %lld: n_fft %d must be a power of two in [max(4, n_samples), %d]", (long long)f.frame_id, f.n_fft, d.n_fft_max);
+    if (f.n_bins > f.n_fft)
+      return fail(RC_EINVAL, "frame %lld: n_bins %d > n_fft %d", (long long)f.frame_id, f.n_bins, f.n_fft);
+  } else if (f.input_kind == RC_INPUT_SPECTRUM) {
+    if (f.n_fft < f.n_bins || f.n_fft < 1)
+      return fail(RC_EINVAL, "frame %lld: n_fft %d must be >= n_bins (it defines the bin spacing)", (long long)f.frame_id, f.n_fft);
+    if (f.spectrum_out)
+      return fail(RC_EINVAL, "frame %lld: spectrum_out needs RAW input", (long long)f.frame_id);
+  } else {
+    return fail(RC_EINVAL, "frame %lld: unknown input_kind %d", (long long)f.frame_id, (int)f.input_kind);
+  }
+  return RC_OK;
+}
+
+// Largest channel-group size (16, 8, 4, 2 or 1) dividing n_ch whose channels
+// share the TX position in every chirp.
+int tx_group(const rc_frame& f) {
+  for (int g : {16, 8, 4, 2}) {
+    if (f.n_channels % g) continue;
+    bool ok = true;
+    for (int64_t m = 0; m < f.n_chirps && ok; ++m)
+      for (int c0 = 0; c0 < f.n_channels && ok; c0 += g)
+        for (int j = 1; j < g && ok; ++j) {
+          const float* a = f.q_tx + ((m * f.n_channels) + c0) * 2;
+          const float* b = f.q_tx + ((m * f.n_channels) + c0 + j) * 2;
+          ok = a[0] == b[0] && a[1] == b[1];
+        }
+    if (ok) return g;
+  }
+  return 1;
+}
+
+rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
+  const rc_plan_desc& d = p->d;
+  const double c = d.radar.c > 0 ? d.radar.c : 299792458.0;
+  const double mu = d.radar.bandwidth / d.radar.t_chirp;
+  const double df = f.fs / f.n_fft;
+  const double a1 = mu / (c * df);
+  const double kd = d.radar.f0 / (c * df);
+  const int64_t rows = (int64_t)f.n_chirps * f.n_channels;
+  const int64_t n_pix = (int64_t)f.n_rows * f.n_cols;
+
+  // geometry staging: rowgeo float4 per (m, ch), then w_sar, then w_range
+  float* g = s.staging;
+  double st_x = 0, st_y = 0, sr_x = 0, sr_y = 0;
+  float tlx = INFINITY, tly = INFINITY, thx = -INFINITY, thy = -INFINITY;
+  float rlx = INFINITY, rly = INFINITY, rhx = -INFINITY, rhy = -INFINITY;
+  for (int64_t r = 0; r < rows; ++r) {
+    const float tx = f.q_tx[2 * r], ty = f.q_tx[2 * r + 1];
+    const float rx = f.q_rx[2 * r], ry = f.q_rx[2 * r + 1];
+    if (!std::isfinite(tx) || !std::isfinite(ty) || !std::isfinite(rx) || !std::isfinite(ry))
+      return fail(RC_EINVAL, "frame %lld: non-finite antenna position", (long long)f.frame_id);
+    g[4 * r + 0] = tx;
+    g[4 * r + 1] = ty;
+    g[4 * r + 2] = rx;
+    g[4 * r + 3] = ry;
+    st_x += tx; st_y += ty; sr_x += rx; sr_y += ry;
+    tlx = std::min(tlx, tx); tly = std::min(tly, ty); thx = std::max(thx, tx); thy = std::max(thy, ty);
+    rlx = std::min(rlx, rx); rly = std::min(rly, ry); rhx = std::max(rhx, rx); rhy = std::max(rhy, ry);
+  }
+  double vx = 0, vy = 0;
+  for (int m = 0; m < f.n_chirps; ++m) {
+    vx += f.vel[2 * m];
+    vy += f.vel[2 * m + 1];
+  }
+  vx /= f.n_chirps;
+  vy /= f.n_chirps;
+  float* w_sar = g + 4 * rows;
+  make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
+  float* w_range = w_sar + f.n_chirps;
+  const int n_s = f.input_kind == RC_INPUT_RAW ? f.n_samples : 0;
+  make_window(d.range_window, d.range_kaiser_beta, n_s, w_range);
+  const size_t geo_bytes = (size_t)(4 * rows + f.n_chirps + n_s) * sizeof(float);
+  RC_HIP(hipMemcpyAsync(s.rowgeo, s.staging, geo_bytes, hipMemcpyHostToDevice, st));
+  const float* d_wsar = reinterpret_cast<const float*>(s.rowgeo) + 4 * rows;
+  const float* d_wrange = d_wsar + f.n_chirps;
+
+  const bool timed = d.stage_timing != 0;
+  if (timed) RC_HIP(hipEventRecord(s.stage_ev[0], st));
+
+  // 1. beat spectrum -> interpolation table
+  if (f.input_kind == RC_INPUT_RAW) {
+    rc::RangeArgs ra{};
+    ra.raw = static_cast<const float2*>(f.data);
+    ra.w_range = d_wrange;
+    ra.w_sar = d_wsar;
+    ra.twiddle = p->twiddle;
+    ra.tw_log2 = p->tw_log2;
+    ra.pairs = s.pairs;
+    ra.spectrum = static_cast<float2*>(f.spectrum_out);
+    ra.rows = rows;
+    ra.n_s = f.n_samples;
+    ra.n_fft = f.n_fft;
+    ra.log2n = ilog2(f.n_fft);
+    ra.n_bins = f.n_bins;
+    ra.n_ch = f.n_channels;
+    RC_HIP(rc::launch_range_compress(ra, st));
+  } else {
+    rc::PairArgs pa{static_cast<const float2*>(f.data), d_wsar, s.pairs, rows, f.n_bins, f.n_channels};
+    RC_HIP(rc::launch_spectrum_pairs(pa, st));
+  }
+
+  if (timed) RC_HIP(hipEventRecord(s.stage_ev[1], st));
+
+  // 2. Doppler table (Sec. III-D)
+  const float2* pix = reinterpret_cast<const float2*>(f.pixels);
+  rc::TableArgs ta{};
+  ta.pix = pix;
+  ta.n_pix = n_pix;
+  ta.qt_x = st_x / rows; ta.qt_y = st_y / rows;
+  ta.qr_x = sr_x / rows; ta.qr_y = sr_y / rows;
+  ta.v_x = vx; ta.v_y = vy;
+  ta.kd = kd;
+  ta.fd = s.fd;
+  RC_HIP(rc::launch_doppler_table(ta, st));
+  if (f.doppler_out)
+    RC_HIP(hipMemcpyAsync(f.doppler_out, s.fd, n_pix * sizeof(float), hipMemcpyDeviceToDevice, st));
+
+  if (timed) RC_HIP(hipEventRecord(s.stage_ev[2], st));
+
+  // 3. back-projection (Alg. 2)
+  float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
+  rc::BpArgs ba{};
+  ba.pix = pix;
+  ba.fd = s.fd;
+  ba.pairs = s.pairs;
+  ba.rowgeo = s.rowgeo;
+  ba.out = img;
+  ba.n_chirps = f.n_chirps;
+  ba.n_ch = f.n_channels;
+  ba.n_bins = f.n_bins;
+  ba.chg = tx_group(f);
+  ba.n_rows = f.n_rows;
+  ba.n_cols = f.n_cols;
+  ba.a1 = (float)a1;
+  ba.inv_lam = (float)(d.radar.f0 / c);
+  ba.tx_lo_x = tlx; ba.tx_lo_y = tly; ba.tx_hi_x = thx; ba.tx_hi_y = thy;
+  ba.rx_lo_x = rlx; ba.rx_lo_y = rly; ba.rx_hi_x = rhx; ba.rx_hi_y = rhy;
+  // single-precision error of an index a1 d_hyp + f_doppler <= n_bins is a few
+  // ulps of n_bins; the margin keeps such waves on the range-tested path
+  ba.f_margin = (float)(1e-3 + 64.0 * f.n_bins * std::ldexp(1.0, -24));
+  RC_HIP(rc::launch_backproject(ba, st));
+  if (timed) RC_HIP(hipEventRecord(s.stage_ev[3], st));
+
+  // 4. CA-CFAR + ordered compaction, then the asynchronous read-back
+  const int h = d.cfar_guard + d.cfar_train;
+  const int n_train = (2 * h + 1) * (2 * h + 1) - (2 * d.cfar_guard + 1) * (2 * d.cfar_guard + 1);
+  const double alpha = n_train * (std::pow(d.cfar_pfa, -1.0 / n_train) - 1.0);
+  const int wpr = (f.n_cols + 63) / 64;
+  rc::CfarArgs ca{img, f.n_rows, f.n_cols, d.cfar_guard, d.cfar_train, alpha / n_train,
+                  d.cfar_margin_rel, s.mask, wpr, s.det_cell};
+  RC_HIP(rc::launch_cfar(ca, st));
+  rc::CompactArgs pa{s.mask, s.det_cell, f.n_rows, f.n_cols, wpr, s.det_out,
+                     (int64_t)d.max_detections, s.det_count};
+  RC_HIP(rc::launch_compact(pa, st));
+  if (timed) RC_HIP(hipEventRecord(s.stage_ev[4], st));
+  RC_HIP(hipMemcpyAsync(s.h_count, s.det_count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  const int prefix = std::min(kDetPrefix, d.max_detections);
+  RC_HIP(hipMemcpyAsync(s.h_det, s.det_out, prefix * sizeof(rc_detection), hipMemcpyDeviceToHost, st));
+  RC_HIP(hipEventRecord(s.done, st));
+
+  s.busy = true;
+  s.frame_id = f.frame_id;
+  s.n_rows = f.n_rows;
+  s.n_cols = f.n_cols;
+  s.image_used = img;
+  return RC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes) {
+  rc_status st = validate_desc(desc);
+  if (st != RC_OK) return st;
+  if (!bytes) return fail(RC_EINVAL, "bytes is NULL");
+  *bytes = (int64_t)slot_sizes(*desc).total();
+  return RC_OK;
+}
+
+rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
+  g_err.clear();
+  if (!out) return fail(RC_EINVAL, "out is NULL");
+  *out = nullptr;
+  rc_status st = validate_desc(desc);
+  if (st != RC_OK) return st;
+  const SlotSizes sz = slot_sizes(*desc);
+  const size_t per_slot = sz.total();
+  const size_t tw_bytes = (size_t)desc->n_fft_max / 2 * sizeof(float2);
+  const size_t need = per_slot * desc->max_frames_in_flight + tw_bytes;
+  if (desc->hbm_budget_bytes > 0 && need > (size_t)desc->hbm_budget_bytes)
+    return fail(RC_ENOMEM, "plan needs %zu bytes of device memory, budget is %lld", need,
+                (long long)desc->hbm_budget_bytes);
+
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(RC_ENOMEM, "host allocation failed");
+  p->d = *desc;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(RC_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  // twiddles exp(-2 pi i k / n_fft_max), k < n_fft_max / 2, evaluated in double
+  p->tw_log2 = ilog2(desc->n_fft_max);
+  {
+    std::vector<float2> tw(desc->n_fft_max / 2);
+    for (size_t k = 0; k < tw.size(); ++k) {
+      const double a = -2.0 * kPi * (double)k / desc->n_fft_max;
+      tw[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    e = hipMalloc(&p->twiddle, tw_bytes);
+    if (e == hipSuccess) e = hipMemcpy(p->twiddle, tw.data(), tw_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(e == hipErrorOutOfMemory ? RC_ENOMEM : RC_EHIP, "twiddle table: %s", hipGetErrorString(e));
+    }
+  }
+  p->slots.resize(desc->max_frames_in_flight);
+  const size_t rows = (size_t)desc->n_chirps_max * desc->n_channels_max;
+  const size_t geo_bytes = (rows * 4 + desc->n_chirps_max + desc->n_samples_max) * sizeof(float);
+  for (Slot& s : p->slots) {
+    char* base = nullptr;
+    e = hipMalloc(&base, per_slot);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(RC_ENOMEM, "device allocation of %zu bytes per slot failed: %s", per_slot,
+                  hipGetErrorString(e));
+    }
+    size_t off = 0;
+    auto take = [&](size_t n) { char* q = base + off; off += n; return q; };
+    s.pairs = reinterpret_cast<float4*>(take(sz.pairs));
+    s.rowgeo = reinterpret_cast<float4*>(take(sz.geo));
+    s.fd = reinterpret_cast<float*>(take(sz.fd));
+    s.image = reinterpret_cast<float2*>(take(sz.image));
+    s.mask = reinterpret_cast<unsigned long long*>(take(sz.mask));
+    s.det_cell = reinterpret_cast<rc_detection*>(take(sz.det_cell));
+    s.det_out = reinterpret_cast<rc_detection*>(take(sz.det_out));
+    s.det_count = reinterpret_cast<int64_t*>(take(64));
+    e = hipHostMalloc(reinterpret_cast<void**>(&s.staging), geo_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) {
+      const size_t hb = 64 + (size_t)std::min(kDetPrefix, desc->max_detections) * sizeof(rc_detection);
+      e = hipHostMalloc(reinterpret_cast<void**>(&s.h_count), hb, hipHostMallocDefault);
+      if (e == hipSuccess) s.h_det = reinterpret_cast<rc_detection*>(reinterpret_cast<char*>(s.h_count) + 64);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    if (desc->stage_timing)
+      for (hipEvent_t& ev : s.stage_ev)
+        if (e == hipSuccess) e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(RC_ENOMEM, "pinned host allocation / event creation failed: %s", hipGetErrorString(e));
+    }
+  }
+  *out = p;
+  return RC_OK;
+}
+
+rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames, void* stream) {
+  g_err.clear();
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p) return fail(RC_EINVAL, "plan is NULL");
+  if (n_frames < 0 || (n_frames > 0 && !frames)) return fail(RC_EINVAL, "bad frame array");
+  int free_slots = 0;
+  for (const Slot& s : p->slots) free_slots += !s.busy;
+  if (n_frames > free_slots)
+    return fail(RC_ENOTREADY, "%d frames but only %d free slots", n_frames, free_slots);
+  for (int i = 0; i < n_frames; ++i) {
+    rc_status st = validate_frame(p, frames[i]);
+    if (st != RC_OK) return st;
+    if (find_slot(p, frames[i].frame_id))
+      return fail(RC_EINVAL, "frame id %lld is already in flight", (long long)frames[i].frame_id);
+    for (int j = 0; j < i; ++j)
+      if (frames[j].frame_id == frames[i].frame_id)
+        return fail(RC_EINVAL, "frame id %lld repeated in the batch", (long long)frames[i].frame_id);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < n_frames; ++i) {
+    Slot* s = nullptr;
+    for (Slot& c : p->slots)
+      if (!c.busy) { s = &c; break; }
+    rc_status r = enqueue_frame(p, *s, frames[i], st);
+    if (r != RC_OK) return r;
+  }
+  return RC_OK;
+}
+
+rc_status rc_poll(void* plan, int64_t frame_id) {
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p) return fail(RC_EINVAL, "plan is NULL");
+  Slot* s = find_slot(p, frame_id);
+  if (!s) return fail(RC_ENOTFOUND, "frame %lld is not in flight", (long long)frame_id);
+  hipError_t e = hipEventQuery(s->done);
+  if (e == hipSuccess) return RC_OK;
+  if (e == hipErrorNotReady) return RC_ENOTREADY;
+  return fail(RC_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+}
+
+rc_status rc_detections(void* plan, int64_t frame_id, rc_detection* dst, int64_t cap, int64_t* n_out) {
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p || !n_out || cap < 0 || (cap > 0 && !dst)) return fail(RC_EINVAL, "bad arguments");
+  Slot* s = find_slot(p, frame_id);
+  if (!s) return fail(RC_ENOTFOUND, "frame %lld is not in flight", (long long)frame_id);
+  RC_HIP(hipEventSynchronize(s->done));
+  const int64_t n = *s->h_count;
+  *n_out = n;
+  const int64_t avail = std::min<int64_t>(n, p->d.max_detections);
+  const int64_t ncopy = std::min<int64_t>(avail, cap);
+  const int64_t pre = std::min<int64_t>(ncopy, std::min(kDetPrefix, p->d.max_detections));
+  if (pre > 0) std::memcpy(dst, s->h_det, pre * sizeof(rc_detection));
+  if (ncopy > pre)
+    RC_HIP(hipMemcpy(dst + pre, s->det_out + pre, (ncopy - pre) * sizeof(rc_detection), hipMemcpyDeviceToHost));
+  if (ncopy < n)
+    return fail(RC_ETRUNC, "frame %lld has %lld detections, %lld copied", (long long)frame_id,
+                (long long)n, (long long)ncopy);
+  return RC_OK;
+}
+
+rc_status rc_image(void* plan, int64_t frame_id, void* dst, int64_t cap_pixels, void* stream) {
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p || !dst) return fail(RC_EINVAL, "bad arguments");
+  Slot* s = find_slot(p, frame_id);
+  if (!s) return fail(RC_ENOTFOUND, "frame %lld is not in flight", (long long)frame_id);
+  const int64_t n = (int64_t)s->n_rows * s->n_cols;
+  if (cap_pixels < n) return fail(RC_ETRUNC, "image has %lld pixels, capacity %lld", (long long)n, (long long)cap_pixels);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  RC_HIP(hipStreamWaitEvent(st, s->done, 0));
+  if (dst != s->image_used)
+    RC_HIP(hipMemcpyAsync(dst, s->image_used, n * sizeof(float2), hipMemcpyDeviceToDevice, st));
+  return RC_OK;
+}
+
+rc_status rc_stage_times(void* plan, int64_t frame_id, float* ms4) {
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p || !ms4) return fail(RC_EINVAL, "bad arguments");
+  if (!p->d.stage_timing) return fail(RC_EINVAL, "plan was created without stage_timing");
+  Slot* s = find_slot(p, frame_id);
+  if (!s) return fail(RC_ENOTFOUND, "frame %lld is not in flight", (long long)frame_id);
+  RC_HIP(hipEventSynchronize(s->done));
+  for (int i = 0; i < 4; ++i) RC_HIP(hipEventElapsedTime(&ms4[i], s->stage_ev[i], s->stage_ev[i + 1]));
+  return RC_OK;
+}
+
+rc_status rc_frame_release(void* plan, int64_t frame_id) {
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p) return fail(RC_EINVAL, "plan is NULL");
+  Slot* s = find_slot(p, frame_id);
+  if (!s) return fail(RC_ENOTFOUND, "frame %lld is not in flight", (long long)frame_id);
+  RC_HIP(hipEventSynchronize(s->done));
+  s->busy = false;
+  s->frame_id = -1;
+  return RC_OK;
+}
+
+rc_status rc_plan_destroy(void* plan) {
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p) return fail(RC_EINVAL, "plan is NULL");
+  for (Slot& s : p->slots)
+    if (s.busy && s.done) (void)hipEventSynchronize(s.done);
+  free_plan(p);
+  return RC_OK;
+}
+
+const char* rc_last_error(void) { return g_err.c_str(); }
+
+rc_status rc_grid_cartesian(double x0, double dx, int32_t nx, double y0, double dy, int32_t ny, float* xy) {
+  if (nx < 1 || ny < 1 || !xy) return fail(RC_EINVAL, "bad grid arguments");
+  for (int32_t iy = 0; iy < ny; ++iy)
+    for (int32_t ix = 0; ix < nx; ++ix) {
+      const size_t i = (size_t)iy * nx + ix;
+      xy[2 * i] = (float)(x0 + ix * dx);
+      xy[2 * i + 1] = (float)(y0 + iy * dy);
+    }
+  return RC_OK;
+}
+
+rc_status rc_grid_polar_params(const rc_radar* radar, double x0, double x1, double y0, double y1,
+                               double ox, double oy, double aperture_len, double factor, double* out6) {
+  if (!radar || !out6 || !(x1 >= x0) || !(y1 >= y0) || !(y0 > oy) || !(aperture_len > 0) || !(factor > 0) ||
+      !(radar->bandwidth > 0) || !(radar->f0 > 0))
+    return fail(RC_EINVAL, "bad polar grid arguments");
+  const double c = radar->c > 0 ? radar->c : 299792458.0;
+  const double lam = c / radar->f0;
+  const double dr = c / (2.0 * radar->bandwidth) / factor;
+  const double dth = lam / (2.0 * aperture_len) / factor;
+  const double xs[2] = {x0 - ox, x1 - ox}, ys[2] = {y0 - oy, y1 - oy};
+  const double cx = std::min(std::max(0.0, xs[0]), xs[1]);
+  const double r_min = std::hypot(cx, ys[0]);
+  double r_max = 0, th_min = INFINITY, th_max = -INFINITY;
+  for (double x : xs)
+    for (double y : ys) {
+      r_max = std::max(r_max, std::hypot(x, y));
+      const double th = std::atan2(x, y);
+      th_min = std::min(th_min, th);
+      th_max = std::max(th_max, th);
+    }
+  out6[0] = r_min;
+  out6[1] = dr;
+  out6[2] = th_min;
+  out6[3] = dth;
+  out6[4] = std::floor((r_max - r_min) / dr) + 1;
+  out6[5] = std::floor((th_max - th_min) / dth) + 1;
+  return RC_OK;
+}
+
+rc_status rc_grid_polar(double ox, double oy, double r0, double dr, int32_t nr, double th0, double dth,
+                        int32_t nth, float* xy) {
+  if (nr < 1 || nth < 1 || !xy) return fail(RC_EINVAL, "bad grid arguments");
+  for (int32_t it = 0; it < nth; ++it) {
+    const double th = th0 + it * dth;
+    const double s = std::sin(th), c = std::cos(th);
+    for (int32_t ir = 0; ir < nr; ++ir) {
+      const double r = r0 + ir * dr;
+      const size_t i = (size_t)it * nr + ir;
+      xy[2 * i] = (float)(ox + r * s);
+      xy[2 * i + 1] = (float)(oy + r * c);
+    }
+  }
+  return RC_OK;
+}
+
+}  // extern "C"

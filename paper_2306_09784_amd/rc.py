@@ -1,0 +1,332 @@
+"""ctypes binding of librc.so (see include/rc.h).
+
+Argument marshalling only: every step of the SAR pipeline runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.  The
+library must have been built (``python -m paper_2306_09784_amd.build``);
+importing this module without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librc.so")
+
+RC_ABI_VERSION = 1
+
+# rc_status
+RC_OK, RC_EINVAL, RC_ENOMEM, RC_ETRUNC, RC_EHIP, RC_ENOTREADY, RC_ENOTFOUND = range(7)
+STATUS_NAMES = {0: "RC_OK", 1: "RC_EINVAL", 2: "RC_ENOMEM", 3: "RC_ETRUNC", 4: "RC_EHIP",
+                5: "RC_ENOTREADY", 6: "RC_ENOTFOUND"}
+# rc_window_kind
+RC_WIN_RECT, RC_WIN_HANN, RC_WIN_KAISER = 0, 1, 2
+WINDOWS = {"rect": RC_WIN_RECT, "hann": RC_WIN_HANN, "kaiser": RC_WIN_KAISER}
+# rc_precision
+RC_PREC_FP32, RC_PREC_FP32_SPLIT = 0, 1
+# rc_input_kind
+RC_INPUT_RAW, RC_INPUT_SPECTRUM = 0, 1
+RC_DET_NEAR_THRESHOLD = 1
+
+
+class rc_radar(C.Structure):
+    _fields_ = [("f0", C.c_double), ("bandwidth", C.c_double), ("t_chirp", C.c_double),
+                ("c", C.c_double)]
+
+
+class rc_plan_desc(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32),
+        ("radar", rc_radar),
+        ("n_samples_max", C.c_int32),
+        ("n_fft_max", C.c_int32),
+        ("n_bins_max", C.c_int32),
+        ("n_chirps_max", C.c_int32),
+        ("n_channels_max", C.c_int32),
+        ("n_pix_max", C.c_int64),
+        ("max_frames_in_flight", C.c_int32),
+        ("max_detections", C.c_int32),
+        ("range_window", C.c_int),
+        ("range_kaiser_beta", C.c_double),
+        ("sar_window", C.c_int),
+        ("sar_kaiser_beta", C.c_double),
+        ("precision", C.c_int),
+        ("cfar_guard", C.c_int32),
+        ("cfar_train", C.c_int32),
+        ("cfar_pfa", C.c_double),
+        ("cfar_margin_rel", C.c_double),
+        ("hbm_budget_bytes", C.c_int64),
+        ("stage_timing", C.c_int32),
+    ]
+
+
+class rc_frame(C.Structure):
+    _fields_ = [
+        ("frame_id", C.c_int64),
+        ("sensor_id", C.c_int32),
+        ("n_samples", C.c_int32),
+        ("n_fft", C.c_int32),
+        ("n_bins", C.c_int32),
+        ("n_chirps", C.c_int32),
+        ("n_channels", C.c_int32),
+        ("fs", C.c_double),
+        ("input_kind", C.c_int),
+        ("data", C.c_void_p),
+        ("q_tx", C.c_void_p),
+        ("q_rx", C.c_void_p),
+        ("vel", C.c_void_p),
+        ("pixels", C.c_void_p),
+        ("n_rows", C.c_int32),
+        ("n_cols", C.c_int32),
+        ("image_out", C.c_void_p),
+        ("doppler_out", C.c_void_p),
+        ("spectrum_out", C.c_void_p),
+    ]
+
+
+class rc_detection(C.Structure):
+    _fields_ = [("pixel", C.c_int32), ("power", C.c_float), ("threshold", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+DETECTION_DTYPE = np.dtype([("pixel", "<i4"), ("power", "<f4"), ("threshold", "<f4"),
+                            ("flags", "<u4")])
+
+#: every entry point declared in include/rc.h
+ENTRY_POINTS = [
+    "rc_plan_create", "rc_plan_slot_bytes", "rc_process_batch", "rc_poll", "rc_detections",
+    "rc_image", "rc_stage_times", "rc_frame_release", "rc_plan_destroy", "rc_last_error", "rc_grid_cartesian",
+    "rc_grid_polar_params", "rc_grid_polar",
+]
+
+
+class RcError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2306_09784_amd.build`")
+    lib = C.CDLL(_LIB_PATH)
+    i32, i64, vp, dp = C.c_int32, C.c_int64, C.c_void_p, C.POINTER(C.c_double)
+    sig = {
+        "rc_plan_create": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(C.c_void_p)]),
+        "rc_plan_slot_bytes": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(C.c_int64)]),
+        "rc_process_batch": (C.c_int, [vp, C.POINTER(rc_frame), i32, vp]),
+        "rc_poll": (C.c_int, [vp, i64]),
+        "rc_detections": (C.c_int, [vp, i64, C.POINTER(rc_detection), i64, C.POINTER(C.c_int64)]),
+        "rc_image": (C.c_int, [vp, i64, vp, i64, vp]),
+        "rc_stage_times": (C.c_int, [vp, i64, C.POINTER(C.c_float)]),
+        "rc_frame_release": (C.c_int, [vp, i64]),
+        "rc_plan_destroy": (C.c_int, [vp]),
+        "rc_last_error": (C.c_char_p, []),
+        "rc_grid_cartesian": (C.c_int, [C.c_double, C.c_double, i32, C.c_double, C.c_double, i32, vp]),
+        "rc_grid_polar_params": (C.c_int, [C.POINTER(rc_radar), C.c_double, C.c_double, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, dp]),
+        "rc_grid_polar": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, i32, C.c_double,
+                                    C.c_double, i32, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.rc_last_error().decode()
+
+
+def check(status: int, where: str):
+    if status != RC_OK:
+        raise RcError(status, where, last_error())
+
+
+# ---------------------------------------------------------------------------
+# Grids (host)
+# ---------------------------------------------------------------------------
+def grid_cartesian(x0: float, dx: float, nx: int, y0: float, dy: float, ny: int) -> np.ndarray:
+    out = np.empty((ny * nx, 2), dtype=np.float32)
+    check(lib.rc_grid_cartesian(x0, dx, nx, y0, dy, ny, out.ctypes.data), "rc_grid_cartesian")
+    return out
+
+
+def grid_polar_params(radar: dict, box, origin, aperture_len: float, factor: float = 2.5) -> dict:
+    r = rc_radar(radar["f0"], radar["bandwidth"], radar["t_chirp"], radar.get("c", 0.0))
+    out = (C.c_double * 6)()
+    check(lib.rc_grid_polar_params(C.byref(r), box[0], box[1], box[2], box[3], origin[0], origin[1],
+                                   aperture_len, factor, out), "rc_grid_polar_params")
+    return {"r0": out[0], "dr": out[1], "th0": out[2], "dth": out[3], "nr": int(out[4]),
+            "nth": int(out[5]), "ox": float(origin[0]), "oy": float(origin[1])}
+
+
+def grid_polar(ox, oy, r0, dr, nr, th0, dth, nth) -> np.ndarray:
+    out = np.empty((nth * nr, 2), dtype=np.float32)
+    check(lib.rc_grid_polar(ox, oy, r0, dr, nr, th0, dth, nth, out.ctypes.data), "rc_grid_polar")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Plans
+# ---------------------------------------------------------------------------
+@dataclass
+class PlanConfig:
+    radar: dict
+    n_samples_max: int
+    n_fft_max: int
+    n_bins_max: int
+    n_chirps_max: int
+    n_channels_max: int
+    n_pix_max: int
+    max_frames_in_flight: int = 2
+    max_detections: int = 65536
+    range_window: str = "hann"
+    range_kaiser_beta: float = 4.0
+    sar_window: str = "hann"
+    sar_kaiser_beta: float = 4.0
+    precision: int = RC_PREC_FP32
+    cfar_guard: int = 2
+    cfar_train: int = 8
+    cfar_pfa: float = 1e-4
+    cfar_margin_rel: float = 3e-2
+    hbm_budget_bytes: int = 0
+    stage_timing: bool = False
+
+    def desc(self) -> rc_plan_desc:
+        r = self.radar
+        return rc_plan_desc(
+            RC_ABI_VERSION, rc_radar(r["f0"], r["bandwidth"], r["t_chirp"], r.get("c", 0.0)),
+            self.n_samples_max, self.n_fft_max, self.n_bins_max, self.n_chirps_max,
+            self.n_channels_max, self.n_pix_max, self.max_frames_in_flight, self.max_detections,
+            WINDOWS[self.range_window], self.range_kaiser_beta, WINDOWS[self.sar_window],
+            self.sar_kaiser_beta, self.precision, self.cfar_guard, self.cfar_train, self.cfar_pfa,
+            self.cfar_margin_rel, self.hbm_budget_bytes, int(self.stage_timing))
+
+
+def slot_bytes(cfg: PlanConfig) -> int:
+    out = C.c_int64()
+    d = cfg.desc()
+    check(lib.rc_plan_slot_bytes(C.byref(d), C.byref(out)), "rc_plan_slot_bytes")
+    return out.value
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Plan:
+    """Owns an rc plan.  Frames are described by plain dicts/arrays; device
+    buffers are torch tensors on the current device."""
+
+    def __init__(self, cfg: PlanConfig):
+        self.cfg = cfg
+        self._desc = cfg.desc()
+        h = C.c_void_p()
+        check(lib.rc_plan_create(C.byref(self._desc), C.byref(h)), "rc_plan_create")
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if self.handle:
+            check(lib.rc_plan_destroy(self.handle), "rc_plan_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def make_frame(frame_id: int, *, data, q_tx: np.ndarray, q_rx: np.ndarray, vel: np.ndarray,
+                   pixels, n_rows: int, n_cols: int, n_bins: int, n_fft: int, fs: float,
+                   n_samples: int = 0, input_kind: int = RC_INPUT_RAW, image_out=None,
+                   doppler_out=None, spectrum_out=None, sensor_id: int = 0) -> rc_frame:
+        """Builds an rc_frame.  q_tx, q_rx, vel must be C-contiguous float32
+        host arrays that stay alive until rc_process_batch returns."""
+        for a in (q_tx, q_rx, vel):
+            if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags.c_contiguous):
+                raise TypeError("q_tx, q_rx and vel must be C-contiguous float32 numpy arrays")
+        M, CH = q_tx.shape[0], q_tx.shape[1]
+        if q_tx.shape != (M, CH, 2) or q_rx.shape != (M, CH, 2) or vel.shape != (M, 2):
+            raise ValueError("geometry shapes must be q [M, CH, 2], vel [M, 2]")
+        return rc_frame(frame_id, sensor_id, n_samples, n_fft, n_bins, M, CH, fs, input_kind,
+                        _ptr(data), q_tx.ctypes.data, q_rx.ctypes.data, vel.ctypes.data,
+                        _ptr(pixels), n_rows, n_cols, _ptr(image_out), _ptr(doppler_out),
+                        _ptr(spectrum_out))
+
+    def process(self, frames, stream=None) -> int:
+        arr = (rc_frame * len(frames))(*frames)
+        st = lib.rc_process_batch(self.handle, arr, len(frames), _stream_handle(stream))
+        if st != RC_OK:
+            raise RcError(st, "rc_process_batch", last_error())
+        return st
+
+    def try_process(self, frames, stream=None) -> int:
+        """Like process() but returns RC_ENOTREADY instead of raising it."""
+        arr = (rc_frame * len(frames))(*frames)
+        st = lib.rc_process_batch(self.handle, arr, len(frames), _stream_handle(stream))
+        if st not in (RC_OK, RC_ENOTREADY):
+            raise RcError(st, "rc_process_batch", last_error())
+        return st
+
+    def poll(self, frame_id: int) -> bool:
+        st = lib.rc_poll(self.handle, frame_id)
+        if st == RC_OK:
+            return True
+        if st == RC_ENOTREADY:
+            return False
+        raise RcError(st, "rc_poll", last_error())
+
+    def detections(self, frame_id: int, cap: Optional[int] = None) -> np.ndarray:
+        if cap is None:
+            cap = self.cfg.max_detections
+        buf = np.zeros(cap, dtype=DETECTION_DTYPE)
+        n = C.c_int64()
+        st = lib.rc_detections(self.handle, frame_id,
+                               buf.ctypes.data_as(C.POINTER(rc_detection)), cap, C.byref(n))
+        if st not in (RC_OK, RC_ETRUNC):
+            raise RcError(st, "rc_detections", last_error())
+        if st == RC_ETRUNC:
+            raise RcError(st, "rc_detections", last_error())
+        return buf[: n.value].copy()
+
+    def image(self, frame_id: int, dst, stream=None):
+        check(lib.rc_image(self.handle, frame_id, _ptr(dst), dst.numel(), _stream_handle(stream)),
+              "rc_image")
+
+    def stage_times(self, frame_id: int) -> np.ndarray:
+        """Device ms of (range compression, tables, back-projection, detection)."""
+        out = (C.c_float * 4)()
+        check(lib.rc_stage_times(self.handle, frame_id, out), "rc_stage_times")
+        return np.array(out[:], dtype=np.float64)
+
+    def release(self, frame_id: int):
+        check(lib.rc_frame_release(self.handle, frame_id), "rc_frame_release")

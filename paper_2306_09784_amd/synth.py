@@ -230,7 +230,7 @@ def beat_signal(scat_pos, scat_amp, q_tx, q_rx, vel, n_samples: int, fs: float,
         cyc = ph0[..., None] + fb[..., None] * k                 # [S, M, CH, K]
         cyc = torch.remainder(cyc, 1.0)
         tone = torch.polar(torch.ones_like(cyc), 2.0 * math.pi * cyc)
-        out += torch.einsum("s,smck->mck", a, tone)
+        out += (a[:, None, None, None] * tone).sum(0)
     return out
 
 

@@ -1,0 +1,155 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports every
+entry point rc.h declares, the ctypes mirror has the C layout, descriptor
+validation and the host grid generators."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_09784_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rc.h")
+LIB = os.path.join(ROOT, "paper_2306_09784_amd", "librc.so")
+
+
+@pytest.fixture(scope="module")
+def rc():
+    if not os.path.exists(LIB):
+        from paper_2306_09784_amd import build
+
+        build.build()
+    from paper_2306_09784_amd import rc as mod
+
+    return mod
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_entry_point(rc):
+    declared = _declared_functions()
+    assert "rc_plan_create" in declared and "rc_process_batch" in declared
+    lib = C.CDLL(LIB)
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(rc.ENTRY_POINTS) == declared
+
+
+_LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "rc.h"
+#define P(T, F) printf(#T "." #F " %zu\n", offsetof(T, F));
+int main(void) {
+  printf("rc_radar %zu\nrc_plan_desc %zu\nrc_frame %zu\nrc_detection %zu\n",
+         sizeof(rc_radar), sizeof(rc_plan_desc), sizeof(rc_frame), sizeof(rc_detection));
+  P(rc_plan_desc, radar) P(rc_plan_desc, n_pix_max) P(rc_plan_desc, range_window)
+  P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision)
+  P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
+  P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
+  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out)
+  P(rc_detection, threshold) P(rc_detection, flags)
+  return 0;
+}
+"""
+
+
+def test_ctypes_layout_matches_header(rc, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    assert int(got["rc_radar"]) == C.sizeof(rc.rc_radar)
+    assert int(got["rc_plan_desc"]) == C.sizeof(rc.rc_plan_desc)
+    assert int(got["rc_frame"]) == C.sizeof(rc.rc_frame)
+    assert int(got["rc_detection"]) == C.sizeof(rc.rc_detection) == rc.DETECTION_DTYPE.itemsize
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(getattr(rc, t), f).offset == int(val), key
+
+
+def _cfg(rc, **kw):
+    base = dict(radar=synth.RADAR, n_samples_max=256, n_fft_max=512, n_bins_max=256, n_chirps_max=128,
+                n_channels_max=4, n_pix_max=65536)
+    base.update(kw)
+    return rc.PlanConfig(**base)
+
+
+def test_descriptor_validation(rc):
+    good = rc.slot_bytes(_cfg(rc))
+    # pairs (16 B/bin) + image + tables per pixel dominate the slot
+    assert good >= 128 * 4 * 256 * 16 + 65536 * (8 + 4 + 8 + 16)
+    bad = [dict(n_fft_max=500), dict(n_fft_max=8192, n_samples_max=256), dict(n_bins_max=1024),
+           dict(n_samples_max=1024), dict(cfar_guard=10, cfar_train=10), dict(cfar_pfa=1.5),
+           dict(max_frames_in_flight=0), dict(precision=7), dict(range_window="bogus")]
+    for kw in bad:
+        with pytest.raises((rc.RcError, KeyError)) as ei:
+            rc.slot_bytes(_cfg(rc, **kw))
+        if isinstance(ei.value, rc.RcError):
+            assert ei.value.status == rc.RC_EINVAL, kw
+    d = _cfg(rc).desc()
+    d.abi_version = 99
+    h = C.c_void_p()
+    assert rc.lib.rc_plan_create(C.byref(d), C.byref(h)) == rc.RC_EINVAL
+    assert "abi_version" in rc.last_error()
+
+
+def test_budget_rejection_before_any_device_call(rc):
+    cfg = _cfg(rc, hbm_budget_bytes=1 << 20)
+    with pytest.raises(rc.RcError) as ei:
+        rc.Plan(cfg)
+    assert ei.value.status == rc.RC_ENOMEM
+
+
+def test_null_arguments(rc):
+    assert rc.lib.rc_process_batch(None, None, 0, None) == rc.RC_EINVAL
+    assert rc.lib.rc_poll(None, 1) == rc.RC_EINVAL
+    assert rc.lib.rc_plan_destroy(None) == rc.RC_EINVAL
+
+
+def test_cartesian_grid_matches_oracle(rc):
+    g = rc.grid_cartesian(-15.0, 0.025, 1201, 1.0, 0.025, 1201)
+    o = O.cartesian_grid(-15.0, 0.025, 1201, 1.0, 0.025, 1201).astype(np.float32)
+    np.testing.assert_array_equal(g, o)
+
+
+def test_polar_grid_matches_oracle(rc):
+    lam = synth.RADAR["c"] / synth.RADAR["f0"]
+    for box, L in [((-15, 15, 1, 31), 0.13), ((-7.5, 7.5, 1, 16), 0.5), ((2, 9, 3, 20), 1.7)]:
+        p = rc.grid_polar_params(synth.RADAR, box, (0.0, 0.0), L)
+        q = O.polar_grid_params(box, (0.0, 0.0), synth.RADAR["bandwidth"], lam, L)
+        for k in ("r0", "dr", "th0", "dth"):
+            assert p[k] == pytest.approx(q[k], rel=1e-15, abs=1e-15), k
+        assert (p["nr"], p["nth"]) == (q["nr"], q["nth"])
+        if p["nr"] * p["nth"] > 4_000_000:
+            continue
+        g = rc.grid_polar(p["ox"], p["oy"], p["r0"], p["dr"], p["nr"], p["th0"], p["dth"], p["nth"])
+        o = O.polar_grid(q["ox"], q["oy"], q["r0"], q["dr"], q["nr"], q["th0"], q["dth"], q["nth"])
+        # both round the same double expression once; libm and numpy may differ by
+        # one double ulp in sin/cos, which can move a float by at most one ulp
+        diff = np.abs(g.astype(np.float64) - o.astype(np.float32).astype(np.float64))
+        ulp = np.spacing(np.abs(o).astype(np.float32)).astype(np.float64)
+        assert np.all(diff <= ulp)
+
+
+def test_polar_pixel_count_reported():
+    """The paper's 165 061 polar pixels are not reproducible from the text
+    (aperture length unstated); record what the grid rule gives at the paper's
+    combined setting (1024 chirps at 1.2 m/s -> L = 0.131 m)."""
+    lam = synth.RADAR["c"] / synth.RADAR["f0"]
+    L = 1024 * synth.RADAR["t_pri"] * 1.2
+    q = O.polar_grid_params((-15, 15, 1, 31), (0.0, 0.0), synth.RADAR["bandwidth"], lam, L)
+    n = q["nr"] * q["nth"]
+    assert 100_000 < n < 400_000

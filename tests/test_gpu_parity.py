@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, stage
+by stage and end to end, on seeded synthetic frames.
+
+Tolerances (derivation in the design notes):
+  * range spectrum, FP32 FFT: relative L2 error <= 1e-5 per frame;
+  * Doppler table (double evaluation, rounded once): <= 1e-6 bins;
+  * back-projection image, FP32 Alg. 2: max |dP| <= BP_TOL * max |P| and,
+    per pixel, |dP| <= 2 pi e_phase * S(p) + BP_FLOOR * max|P| where S(p) is the
+    oracle's sum of term magnitudes and e_phase the single-precision phase
+    error bound 2^-21 * d_max / lambda (turns);
+  * detections: identical lists except cells whose oracle statistic lies within
+    DET_BAND (relative) of its threshold.
+"""
+import dataclasses
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_09784_amd import synth
+from tests import sar_cases as SC
+
+pytestmark = pytest.mark.gpu
+
+SPEC_TOL = 1e-5
+DOP_TOL = 1e-6
+BP_TOL = 2e-3
+BP_FLOOR = 1e-4
+DET_BAND = 5e-2
+
+
+def _report(name, **vals):
+    path = os.environ.get("RC_REPORT")
+    print(name, vals, flush=True)
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps({"case": name, **vals}) + "\n")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def rc():
+    from paper_2306_09784_amd import rc as mod
+
+    return mod
+
+
+def _phase_bound(frame):
+    corners = np.array([[frame.pix[:, 0].min(), frame.pix[:, 1].min()], [frame.pix[:, 0].max(), frame.pix[:, 1].max()],
+                        [frame.pix[:, 0].min(), frame.pix[:, 1].max()], [frame.pix[:, 0].max(), frame.pix[:, 1].min()]])
+    q = np.concatenate([frame.q_tx.reshape(-1, 2), frame.q_rx.reshape(-1, 2)])
+    d_max = 2 * np.sqrt(((corners[:, None, :] - q[None]) ** 2).sum(-1)).max()
+    lam = synth.RADAR["c"] / synth.RADAR["f0"]
+    return 2.0 ** -21 * d_max / lam + 1e-5
+
+
+def _check_image(name, frame, gpu_img, ora, pix_index=None):
+    P = ora["image"]
+    G = gpu_img if pix_index is None else gpu_img[pix_index]
+    err = np.abs(G.astype(np.complex128) - P)
+    pmax = np.abs(P).max()
+    rel = float(err.max() / pmax)
+    k = ora["k"]
+    pix = frame.pix.astype(np.float64) if pix_index is None else frame.pix.astype(np.float64)[pix_index]
+    S = O.bp_alg2_abs(pix, frame.q_tx, frame.q_rx, ora["doppler"], ora["spectrum"], ora["w_sar"], k["a1"])
+    e_ph = _phase_bound(frame)
+    bound = 2 * math.pi * e_ph * S + BP_FLOOR * pmax
+    worst = float((err / bound).max())
+    _report(name, max_rel=rel, rms_rel=float(np.sqrt(np.mean(err ** 2)) / pmax), bound_ratio=worst,
+            e_phase_turns=e_ph)
+    assert rel <= BP_TOL, f"{name}: max|dP|/max|P| = {rel:.3e}"
+    assert worst <= 1.0, f"{name}: per-pixel bound exceeded by {worst:.3f}"
+
+
+# ---------------------------------------------------------------------------
+# stage parity
+# ---------------------------------------------------------------------------
+def test_range_and_doppler_parity_plain_small(rc, torch):
+    fr = SC.small_frame(nx=64, ny=48)
+    with rc.Plan(SC.plan_config(rc, [fr])) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, want_spectrum=True, want_doppler=True)
+    ora = SC.run_oracle(fr, cfar=None)
+    s, so = out["spectrum"].astype(np.complex128), ora["spectrum"]
+    rel_l2 = float(np.linalg.norm(s - so) / np.linalg.norm(so))
+    row_rel = float((np.abs(s - so).max(-1) / np.abs(so).max(-1)).max())
+    dd = float(np.abs(out["doppler"] - ora["doppler"]).max())
+    _report("range_doppler_small", rel_l2=rel_l2, row_max_rel=row_rel, doppler_abs=dd)
+    assert rel_l2 <= SPEC_TOL
+    assert row_rel <= 10 * SPEC_TOL
+    assert dd <= DOP_TOL
+    _check_image("image_small_64x48", fr, out["image"], ora)
+
+
+@pytest.mark.parametrize("n_tx,n_rx,n_chirps", [(1, 4, 16), (4, 4, 8), (2, 1, 12), (1, 16, 6), (1, 8, 9),
+                                                (1, 2, 10), (1, 1, 1), (3, 1, 5)])
+def test_bp_parity_spectrum_input(rc, torch, n_tx, n_rx, n_chirps):
+    """Alg. 2 alone on a seeded random spectrum over a ragged 37 x 45 lattice
+    (several 16 x 16 tiles plus partial ones); covers every TX-group width."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="bp", n_samples=64, n_chirps=n_chirps,
+                              n_tx=n_tx, n_rx=n_rx, nx=45, ny=37, box=(-4.0, 4.0, 1.5, 7.0),
+                              n_targets=1, noise=False, seed=7 + n_tx * 10 + n_rx)
+    fr = synth.make_frame(cfg)
+    rng = np.random.default_rng(100 + n_tx * 16 + n_rx)
+    spec = synth.random_spectrum(rng, (cfg.n_chirps, cfg.n_channels, fr.n_bins))
+    with rc.Plan(SC.plan_config(rc, [fr])) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, spectrum=spec)
+    ora = SC.run_oracle(fr, spectrum=spec, cfar=None)
+    _check_image(f"bp_spectrum_tx{n_tx}_rx{n_rx}_m{n_chirps}", fr, out["image"], ora)
+
+
+def test_bp_parity_indices_out_of_range(rc, torch):
+    """Too few kept bins: many terms fall outside [0, n_bins - 1] and must
+    contribute zero (range-tested path), others stay in range."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="oor", n_samples=64, n_chirps=8, n_rx=4,
+                              nx=40, ny=40, box=(-6.0, 6.0, 1.0, 13.0), n_targets=1, noise=False, seed=5)
+    fr = synth.make_frame(cfg)
+    fr = dataclasses.replace(fr, n_bins=fr.n_bins // 2)
+    rng = np.random.default_rng(55)
+    spec = synth.random_spectrum(rng, (cfg.n_chirps, cfg.n_channels, fr.n_bins))
+    with rc.Plan(SC.plan_config(rc, [fr])) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, spectrum=spec)
+    ora = SC.run_oracle(fr, spectrum=spec, cfar=None)
+    zero = np.abs(ora["image"]) == 0
+    assert zero.sum() > 100                         # whole pixels beyond the band
+    assert np.all(out["image"][zero] == 0)
+    _check_image("bp_out_of_range", fr, out["image"], ora)
+
+
+@pytest.mark.parametrize("n_rows,n_cols", [(1, 300), (5, 70), (8, 8), (9, 17)])
+def test_bp_parity_small_lattices(rc, torch, n_rows, n_cols):
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="lat", n_samples=32, n_chirps=6, n_rx=4,
+                              nx=n_cols, ny=n_rows, box=(-3.0, 3.0, 2.0, 5.0), n_targets=2, noise=True,
+                              seed=9)
+    fr = synth.make_frame(cfg)
+    with rc.Plan(SC.plan_config(rc, [fr])) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch)
+    ora = SC.run_oracle(fr, cfar=None)
+    _check_image(f"lattice_{n_rows}x{n_cols}", fr, out["image"], ora)
+
+
+# ---------------------------------------------------------------------------
+# end to end
+# ---------------------------------------------------------------------------
+def test_end_to_end_plain_small(rc, torch):
+    """256 samples x 128 chirps x 4 RX on a 256 x 256 grid: image and detections."""
+    fr = SC.small_frame()
+    with rc.Plan(SC.plan_config(rc, [fr])) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch)
+    ora = SC.run_oracle(fr)
+    _check_image("end_to_end_small", fr, out["image"], ora)
+    dets = out["detections"]
+    assert np.all(np.diff(dets["pixel"]) > 0)       # ascending pixel order
+    bad, n_diff = SC.detection_mismatch(dets, ora["cfar"], ora["power"], fr.n_cols, 2, 8, 1e-4, DET_BAND)
+    _report("detections_small", n_gpu=int(len(dets)), n_oracle=int(len(ora["cfar"][0])), n_diff=n_diff,
+            n_outside_band=len(bad))
+    assert not bad, bad[:5]
+    assert len(dets) > 0
+    # reported power / threshold match the oracle's at common cells
+    common, gi, oi = np.intersect1d(dets["pixel"], ora["cfar"][0], return_indices=True)
+    np.testing.assert_allclose(dets["power"][gi], ora["cfar"][1][oi], rtol=0.05)
+    np.testing.assert_allclose(dets["threshold"][gi], ora["cfar"][2][oi], rtol=0.01)
+    # every point target of SNR >= 20 dB is detected within one pixel
+    for tp, a in zip(fr.targets, fr.target_amp):
+        if 20 * np.log10(abs(a)) < 20:
+            continue
+        d = np.hypot(fr.pix[dets["pixel"], 0] - tp[0], fr.pix[dets["pixel"], 1] - tp[1])
+        assert d.min() < 0.15
+
+
+@pytest.mark.slow
+def test_plain_large_sampled_pixels(rc, torch):
+    """Full-size frame (1024 samples x 512 cycles x 16 channels, 1201^2 grid) in
+    the benchmark's launch configuration; oracle on sampled pixels."""
+    fr = synth.make_frame(synth.CONFIGS["plain-large"], device="cuda")
+    with rc.Plan(SC.plan_config(rc, [fr])) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, want_spectrum=True)
+    k = SC.oracle_constants(fr)
+    s = O.range_compress(fr.raw, O.window("hann", fr.cfg.n_samples), fr.n_fft, fr.n_bins)
+    rel_l2 = float(np.linalg.norm(out["spectrum"] - s) / np.linalg.norm(s))
+    _report("range_large", rel_l2=rel_l2)
+    assert rel_l2 <= SPEC_TOL
+    rng = np.random.default_rng(77)
+    idx = np.unique(np.concatenate([rng.integers(0, fr.n_rows * fr.n_cols, 400),
+                                    np.argsort(-np.abs(out["image"]))[:50]]))
+    ora = SC.run_oracle(fr, spectrum=s, pix_index=idx, cfar=None)
+    _check_image("image_large_sampled", fr, out["image"], ora, pix_index=idx)
+
+
+# ---------------------------------------------------------------------------
+# ABI behaviour on the device
+# ---------------------------------------------------------------------------
+def test_abi_errors_on_device(rc, torch):
+    fr = SC.small_frame(nx=32, ny=32)
+    cfg = SC.plan_config(rc, [fr], max_frames_in_flight=1, max_detections=2)
+    with rc.Plan(cfg) as plan:
+        t = SC.to_device(fr, torch)
+        img = torch.empty((32 * 32, 2), dtype=torch.float32, device="cuda")
+        mk = lambda fid, **kw: rc.Plan.make_frame(fid, data=t["raw"], q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel,
+                                                  pixels=t["pix"], n_rows=32, n_cols=32, n_bins=fr.n_bins,
+                                                  n_fft=fr.n_fft, fs=fr.fs, n_samples=fr.cfg.n_samples,
+                                                  image_out=img, **kw)
+        over = mk(1)
+        over.n_fft = fr.n_fft * 2                           # over n_fft_max
+        with pytest.raises(rc.RcError) as ei:
+            plan.process([over])
+        assert ei.value.status == rc.RC_EINVAL
+        bad = mk(2)
+        bad.n_bins = fr.n_bins + 1
+        with pytest.raises(rc.RcError) as ei:
+            plan.process([bad])
+        assert ei.value.status == rc.RC_EINVAL
+        plan.process([mk(3)])
+        assert plan.try_process([mk(4)]) == rc.RC_ENOTREADY  # single slot busy
+        with pytest.raises(rc.RcError) as ei:
+            plan.detections(99)
+        assert ei.value.status == rc.RC_ENOTFOUND
+        import ctypes as C
+        buf = np.zeros(1, dtype=rc.DETECTION_DTYPE)
+        n = C.c_int64()
+        st = rc.lib.rc_detections(plan.handle, 3, buf.ctypes.data_as(C.POINTER(rc.rc_detection)), 1, C.byref(n))
+        assert st == rc.RC_ETRUNC and n.value > 1
+        while not plan.poll(3):
+            pass
+        plan.release(3)
+        plan.process([mk(4)])
+        plan.release(4)
