@@ -28,10 +28,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "radar frames/s and p50/p99 frame latency at 1 MI355X; % HBM roofline"
 
-# gfx950 peak issue rate of non-packed FP32 VALU lane-instructions:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_LANE_OPS = 256 * 64 * 2.4e9
-# sqrt, sin and cos issue at a quarter of the VALU rate
+# gfx950 peak issue rate of FP32 VALU lane-instructions (non-packed): 256 CUs x
+# 128 lanes per clock x 2.4 GHz = 78.6e12/s, i.e. the published 157.3 TFLOP/s
+# FP32 vector peak with an FMA counted as two flops
+VALU_LANE_OPS = 256 * 128 * 2.4e9
+# sqrt, sin and cos issue at a quarter of that rate (measured: 18 vs 60 T/s)
 TRANS_SLOTS = 4.0
 HBM_PEAK_GBS = 8000.0
 
@@ -105,6 +106,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="plain-large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (for HBM counter calibration)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -118,6 +121,15 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.copy_calibration:
+        n = args.copy_calibration << 18
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 3}), flush=True)
+        return 0
     from paper_2306_09784_amd import rc, synth
 
     cfg = synth.CONFIGS[args.workload]

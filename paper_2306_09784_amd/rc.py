@@ -110,6 +110,12 @@ class RcError(RuntimeError):
 
 
 def _load():
+    # librc.so needs libamdhip64.so.7.  Load torch first so that the library
+    # binds to the HIP runtime torch already uses: one runtime per process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2306_09784_amd.build`")
     lib = C.CDLL(_LIB_PATH)
