@@ -3,23 +3,28 @@
 // For every pixel p the lane evaluates, for each chirp m and channel ch,
 //   d_hyp = |p - q_tx(m,ch)| + |p - q_rx(m,ch)|,
 //   f_ind = a1 d_hyp + f_doppler(p)                 (index of s, Sec. III-C),
-//   s_hyp = exp(a2 d_hyp) = exp(-2 pi i d_hyp f0/c)  (carrier phase),
+//   s_hyp = exp(a2 d_hyp) = exp(-2 pi i d_hyp / lambda)  (carrier phase),
 //   P(p) += s_hyp * w_sar[m] * lerp(s[m,ch,:], f_ind),
 // and writes P(p) once.  The chirp window w_sar[m] (Sec. III-B) is folded into
 // the interpolation table by range compression.
 //
-// gfx950 mapping.  The loop is VALU/transcendental bound (three quarter-rate
-// ops per term: sqrt, sin, cos), so the design minimises VALU slots per term:
-//  * per-(m, ch) geometry is wave-uniform and is read with scalar loads;
+// gfx950 mapping.  The loop is bound by VALU issue (three quarter-rate
+// transcendentals per term: sqrt, sin, cos, plus ~15 full-rate instructions),
+// so the design minimises instructions per term:
+//  * geometry is in aperture-local wavelength units, so a path length is its
+//    carrier phase in turns and needs only v_fract before the hardware
+//    sin/cos (which take turns);
+//  * a squared distance is |P|^2 + |q|^2 - 2 P.q: two FMAs and an add with the
+//    per-row uniforms (-2 q, |q|^2), read with scalar loads;
 //  * channels sharing a TX position evaluate d_tx once per group;
-//  * the phase is reduced to a fraction of a turn (v_fract) and fed to the
-//    hardware sin/cos, which take their argument in turns;
 //  * the table holds (s[k], s[k+1] - s[k]) so one 16-byte buffer load and two
 //    FMAs interpolate a term; loads go through a per-row buffer descriptor, so
 //    an index outside the row reads zeros instead of faulting;
 //  * a wave first bounds the index range of all its terms from the bounding
 //    boxes of the antenna positions; if every term is provably inside
-//    [0, n_bins - 1] it runs the loop without the per-term range test.
+//    [0, n_bins - 1] it runs the loop without the per-term range test;
+//  * even and odd channels accumulate into separate registers to shorten the
+//    dependency chains of the multiply-accumulates.
 // A wave covers an 8 x 8 pixel block of the lattice so its gathers of one
 // (m, ch) row touch a handful of neighbouring bins.
 #include "rc_kernels.hpp"
@@ -31,52 +36,119 @@ constexpr int kThreads = 256;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 
-__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
+// Split-phase form: d = |P - q| = R + delta with delta = N / (d + R) and
+// N = |P - q|^2 - R^2 = |q|^2 - 2 P.q (two FMAs), d = sqrt(R^2 + N).  Only
+// delta (|delta| <= |q|) and the reference phase frac(2R) enter the phase, so
+// its rounding error scales with the aperture size, not with the range.
 template <int CHG, bool CHECKED>
-__device__ __forceinline__ void bp_terms(const BpArgs& a, float px, float py, float fdp,
-                                         float& acc_re, float& acc_im) {
+__device__ __forceinline__ void bp_terms_split(const BpArgs& a, const float4 p, const float fb,
+                                               float& out_re, float& out_im) {
   const float nbm1 = (float)(a.n_bins - 1);
-  const unsigned row_bytes = (unsigned)a.n_bins * 16u;
-  for (int m = 0; m < a.n_chirps; ++m) {
-    const int row_m = m * a.n_ch;
-    for (int g = 0; g < a.n_ch; g += CHG) {
-      const int row0 = row_m + g;
-      const float4 q0 = a.rowgeo[row0];
-      const float tx = px - q0.x, ty = py - q0.y;
-      const float d_tx = hw_sqrt(fmaf(tx, tx, ty * ty));
+  const int row_bytes = a.n_bins * 16;
+  const int rows = a.n_chirps * a.n_ch;
+  const size_t gstride = (size_t)CHG * a.n_bins;
+  const float4* rq = a.rowq;
+  const float4* gq = a.grpq;
+  const float4* tab = a.pairs;
+  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+  for (int row0 = 0; row0 < rows; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
+    const float4 t = gq[0];
+    const float nt = fmaf(t.x, p.x, fmaf(t.y, p.y, t.z));
+    const float dlt_tx = nt * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, nt)) + p.z);
 #pragma unroll
-      for (int j = 0; j < CHG; ++j) {
-        const float4 q = a.rowgeo[row0 + j];
-        const float rx = px - q.z, ry = py - q.w;
-        const float d_hyp = d_tx + hw_sqrt(fmaf(rx, rx, ry * ry));
-        const float f = fmaf(a.a1, d_hyp, fdp);
-        int i;
-        float phi;
-        if (CHECKED) {
-          const float fl = floorf(f);
-          phi = f - fl;
-          i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;  // -1: out of the descriptor -> zeros
-        } else {
-          i = (int)f;                                  // f >= 0 here: truncation is floor
-          phi = __builtin_amdgcn_fractf(f);
-        }
-        const float turn = __builtin_amdgcn_fractf(d_hyp * a.inv_lam);
-        const float sn = __builtin_amdgcn_sinf(turn);   // sin(2 pi turn)
-        const float cs = __builtin_amdgcn_cosf(turn);
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(a.pairs + (size_t)(row0 + j) * a.n_bins), (short)0, (int)row_bytes, kRsrcWord3);
-        const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
-        const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
-        const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
-        // (cs - i sn) (vr + i vi)
-        acc_re = fmaf(cs, vr, acc_re);
-        acc_re = fmaf(sn, vi, acc_re);
-        acc_im = fmaf(cs, vi, acc_im);
-        acc_im = fmaf(-sn, vr, acc_im);
+    for (int j = 0; j < CHG; ++j) {
+      const float4 q = rq[j];
+      const float nr = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
+      const float dlt = dlt_tx + nr * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, nr)) + p.z);
+      const float f = fmaf(a.a1, dlt, fb);
+      int i;
+      float phi;
+      if (CHECKED) {
+        const float fl = floorf(f);
+        phi = f - fl;
+        i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;
+      } else {
+        i = (int)f;
+        phi = __builtin_amdgcn_fractf(f);
+      }
+      const float turn = __builtin_amdgcn_fractf(p.w + dlt);
+      const float sn = __builtin_amdgcn_sinf(turn);
+      const float cs = __builtin_amdgcn_cosf(turn);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(tab + (size_t)j * a.n_bins), (short)0, row_bytes, kRsrcWord3);
+      const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
+      const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
+      const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
+      if (j & 1) {
+        re1 = fmaf(cs, vr, re1);
+        re1 = fmaf(sn, vi, re1);
+        im1 = fmaf(cs, vi, im1);
+        im1 = fmaf(-sn, vr, im1);
+      } else {
+        re0 = fmaf(cs, vr, re0);
+        re0 = fmaf(sn, vi, re0);
+        im0 = fmaf(cs, vi, im0);
+        im0 = fmaf(-sn, vr, im0);
       }
     }
   }
+  out_re = re0 + re1;
+  out_im = im0 + im1;
+}
+
+template <int CHG, bool CHECKED>
+__device__ __forceinline__ void bp_terms(const BpArgs& a, const float4 p, const float fdp,
+                                         float& out_re, float& out_im) {
+  const float nbm1 = (float)(a.n_bins - 1);
+  const int row_bytes = a.n_bins * 16;
+  const int rows = a.n_chirps * a.n_ch;
+  const size_t gstride = (size_t)CHG * a.n_bins;
+  const float4* rq = a.rowq;
+  const float4* gq = a.grpq;
+  const float4* tab = a.pairs;
+  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+  for (int row0 = 0; row0 < rows; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
+    const float4 t = gq[0];
+    const float d_tx = __builtin_amdgcn_sqrtf(fmaf(t.x, p.x, fmaf(t.y, p.y, p.z)) + t.z) + p.w;
+#pragma unroll
+    for (int j = 0; j < CHG; ++j) {
+      const float4 q = rq[j];
+      const float d_hyp = d_tx + __builtin_amdgcn_sqrtf(fmaf(q.x, p.x, fmaf(q.y, p.y, p.z)) + q.z);
+      const float f = fmaf(a.a1, d_hyp, fdp);
+      int i;
+      float phi;
+      if (CHECKED) {
+        const float fl = floorf(f);
+        phi = f - fl;
+        i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;  // -1: outside the descriptor -> zeros
+      } else {
+        i = (int)f;                                  // f >= 0 here: truncation is floor
+        phi = __builtin_amdgcn_fractf(f);
+      }
+      const float turn = __builtin_amdgcn_fractf(d_hyp);
+      const float sn = __builtin_amdgcn_sinf(turn);  // sin(2 pi turn)
+      const float cs = __builtin_amdgcn_cosf(turn);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(tab + (size_t)j * a.n_bins), (short)0, row_bytes, kRsrcWord3);
+      const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
+      const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
+      const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
+      // (cs - i sn) (vr + i vi)
+      if (j & 1) {
+        re1 = fmaf(cs, vr, re1);
+        re1 = fmaf(sn, vi, re1);
+        im1 = fmaf(cs, vi, im1);
+        im1 = fmaf(-sn, vr, im1);
+      } else {
+        re0 = fmaf(cs, vr, re0);
+        re0 = fmaf(sn, vi, re0);
+        im0 = fmaf(cs, vi, im0);
+        im0 = fmaf(-sn, vr, im0);
+      }
+    }
+  }
+  out_re = re0 + re1;
+  out_im = im0 + im1;
 }
 
 __device__ __forceinline__ float box_min_dist(float px, float py, float lx, float ly, float hx, float hy) {
@@ -90,7 +162,7 @@ __device__ __forceinline__ float box_max_dist(float px, float py, float lx, floa
   return sqrtf(dx * dx + dy * dy);
 }
 
-template <int CHG>
+template <int CHG, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void bp_kernel(BpArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -108,8 +180,10 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpArgs a) {
   const int rr = r < a.n_rows ? r : a.n_rows - 1;
   const int cc = c < a.n_cols ? c : a.n_cols - 1;
   const int64_t idx = (int64_t)rr * a.n_cols + cc;
-  const float2 p = a.pix[idx];
-  const float fdp = a.fd[idx];
+  const float4 p = a.pixc[idx];
+  // plain form: f_doppler; split form: index of the reference path 2R, from
+  // which f_doppler follows for the range bound
+  const float fdp = SPLIT ? a.fbase[idx] - a.a1 * 2.f * p.z : a.fd[idx];
 
   const float dlo = box_min_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
                     box_min_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
@@ -118,12 +192,28 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpArgs a) {
   const float flo = fmaf(a.a1, dlo, fdp), fhi = fmaf(a.a1, dhi, fdp);
   const bool inside = flo >= a.f_margin && fhi <= (float)(a.n_bins - 1) - a.f_margin;
 
-  float acc_re = 0.f, acc_im = 0.f;
-  if (__all(inside))
-    bp_terms<CHG, false>(a, p.x, p.y, fdp, acc_re, acc_im);
+  float re, im;
+  if (SPLIT) {
+    const float fb = a.fbase[idx];
+    if (__all(inside))
+      bp_terms_split<CHG, false>(a, p, fb, re, im);
+    else
+      bp_terms_split<CHG, true>(a, p, fb, re, im);
+  } else {
+    if (__all(inside))
+      bp_terms<CHG, false>(a, p, fdp, re, im);
+    else
+      bp_terms<CHG, true>(a, p, fdp, re, im);
+  }
+  if (live) a.out[idx] = make_float2(re, im);
+}
+
+template <int CHG>
+void launch_chg(const BpArgs& a, dim3 grid, hipStream_t s) {
+  if (a.split)
+    hipLaunchKernelGGL((bp_kernel<CHG, true>), grid, dim3(kThreads), 0, s, a);
   else
-    bp_terms<CHG, true>(a, p.x, p.y, fdp, acc_re, acc_im);
-  if (live) a.out[idx] = make_float2(acc_re, acc_im);
+    hipLaunchKernelGGL((bp_kernel<CHG, false>), grid, dim3(kThreads), 0, s, a);
 }
 
 }  // namespace
@@ -131,6 +221,7 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpArgs a) {
 hipError_t launch_backproject(const BpArgs& a, hipStream_t s) {
   if (a.n_rows <= 0 || a.n_cols <= 0) return hipSuccess;
   if (a.n_chirps < 1 || a.n_ch < 1 || a.n_bins < 2 || a.chg < 1 || a.n_ch % a.chg != 0 ||
+      (a.split && !a.fbase) ||
       (int64_t)a.n_bins * 16 >= (int64_t)1 << 31 || (int64_t)a.n_chirps * a.n_ch >= (int64_t)1 << 31)
     return hipErrorInvalidValue;
   dim3 grid;
@@ -139,11 +230,11 @@ hipError_t launch_backproject(const BpArgs& a, hipStream_t s) {
   else
     grid = dim3((a.n_cols + kThreads - 1) / kThreads, a.n_rows);
   switch (a.chg) {
-    case 16: hipLaunchKernelGGL(bp_kernel<16>, grid, dim3(kThreads), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(bp_kernel<8>, grid, dim3(kThreads), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(bp_kernel<4>, grid, dim3(kThreads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(bp_kernel<2>, grid, dim3(kThreads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(bp_kernel<1>, grid, dim3(kThreads), 0, s, a); break;
+    case 16: launch_chg<16>(a, grid, s); break;
+    case 8: launch_chg<8>(a, grid, s); break;
+    case 4: launch_chg<4>(a, grid, s); break;
+    case 2: launch_chg<2>(a, grid, s); break;
+    case 1: launch_chg<1>(a, grid, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -40,34 +40,51 @@ struct PairArgs {
 };
 hipError_t launch_spectrum_pairs(const PairArgs& a, hipStream_t s);
 
-// Per-pixel Doppler table in bins from the mean velocity at the aperture
-// centre (evaluated in double, stored as float).
+// Per-pixel tables, evaluated in double and rounded once:
+//  * f_doppler(p) in bins from the mean velocity at the aperture centre;
+//  * the pixel in aperture-local wavelength units, P = (p - c) / lambda, as
+//    float4 (P'.x, P'.y, pp, corr) with P' = float(P), pp = float(|P|^2) and
+//    corr = (|P|^2 - pp) / |P|, the first-order path correction (in turns) for
+//    the rounding of pp that back-projection adds to every two-way path.
 struct TableArgs {
   const float2* pix;
   int64_t n_pix;
   double qt_x, qt_y, qr_x, qr_y;  // mean TX / RX positions
   double v_x, v_y;                // mean velocity
   double kd;                      // f0 / (c df): bins per m/s of radial speed
+  double c_x, c_y;                // aperture centre (origin of the local frame)
+  double inv_lam;                 // 1 / lambda
   float* fd;                      // [n_pix]
+  float4* pixc;                   // [n_pix]
+  // split-phase form: pixc = (P'.x, P'.y, R, frac(2R)) with R = |P| and
+  // fbase = a1 * 2R + f_doppler (the index of the reference path 2R)
+  int split;
+  double a1;                      // bins per wavelength of path
+  float* fbase;                   // [n_pix] (split only)
 };
-hipError_t launch_doppler_table(const TableArgs& a, hipStream_t s);
+hipError_t launch_pixel_tables(const TableArgs& a, hipStream_t s);
 
 // Back-projection (Alg. 2).  One lane per pixel; a wave covers an 8 x 8 block
 // of the lattice (or 1 x 64 for single-row lattices); channels that share a
 // TX position in every chirp form groups of chg channels whose d_tx is
-// evaluated once.
+// evaluated once.  Distances are in wavelengths (a path of d_hyp wavelengths
+// has the carrier phase -2 pi d_hyp), squared distances are formed as
+// pp + |q|^2 - 2 P.q from per-row uniforms.
 struct BpArgs {
-  const float2* pix;      // [n_rows * n_cols]
+  const float4* pixc;     // [n_rows * n_cols]: (P.x, P.y, |P|^2, corr), wavelengths
   const float* fd;        // [n_rows * n_cols], bins
   const float4* pairs;    // [n_chirps * n_ch][n_bins]
-  const float4* rowgeo;   // [n_chirps * n_ch]: (q_tx.x, q_tx.y, q_rx.x, q_rx.y)
+  const float4* rowq;     // [n_chirps * n_ch]: (-2 q_rx.x, -2 q_rx.y, |q_rx|^2, 0)
+  const float4* grpq;     // [n_chirps * n_ch / chg]: (-2 q_tx.x, -2 q_tx.y, |q_tx|^2, 0)
   float2* out;            // [n_rows * n_cols]
+  const float* fbase;     // split form: [n_rows * n_cols] index of the reference path
+  int split;              // 0: plain single precision; 1: split phase (see tables)
   int n_chirps, n_ch, n_bins, chg;
   int n_rows, n_cols;
-  float a1;               // bins per metre of two-way path
-  float inv_lam;          // turns per metre of two-way path (f0 / c)
-  // bounding boxes of all TX / RX positions and the index margin that lets a
-  // wave skip the per-term range test when every term is provably in range
+  float a1;               // bins per wavelength of two-way path
+  // bounding boxes of all TX / RX positions (wavelengths, local frame) and
+  // the index margin that lets a wave skip the per-term range test when every
+  // term is provably in range
   float tx_lo_x, tx_lo_y, tx_hi_x, tx_hi_y;
   float rx_lo_x, rx_lo_y, rx_hi_x, rx_hi_y;
   float f_margin;

@@ -76,8 +76,10 @@ void make_window(rc_window_kind kind, double beta, int n, float* out) {
 struct Slot {
   // device
   float4* pairs = nullptr;
-  float4* rowgeo = nullptr;   // followed by w_sar[n_chirps_max], w_range[n_samples_max]
+  float4* rowgeo = nullptr;   // rowq[rows], grpq[rows], w_sar[n_chirps_max], w_range[n_samples_max]
   float* fd = nullptr;
+  float4* pixc = nullptr;
+  float* fbase = nullptr;
   float2* image = nullptr;
   unsigned long long* mask = nullptr;
   rc_detection* det_cell = nullptr;
@@ -106,18 +108,27 @@ struct Plan {
 };
 
 struct SlotSizes {
-  size_t pairs, geo, fd, image, mask, det_cell, det_out;
-  size_t total() const { return pairs + geo + fd + image + mask + det_cell + det_out + 64; }
+  size_t pairs, geo, fd, pixc, fbase, image, mask, det_cell, det_out;
+  size_t total() const { return pairs + geo + fd + pixc + fbase + image + mask + det_cell + det_out + 64; }
 };
 
 size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// staging/device geometry region: rowq[rows] and grpq[rows] float4, then
+// w_sar[n_chirps_max] and w_range[n_samples_max]
+size_t geo_floats(const rc_plan_desc& d) {
+  const size_t rows = (size_t)d.n_chirps_max * d.n_channels_max;
+  return rows * 8 + d.n_chirps_max + d.n_samples_max;
+}
 
 SlotSizes slot_sizes(const rc_plan_desc& d) {
   SlotSizes s;
   const size_t rows = (size_t)d.n_chirps_max * d.n_channels_max;
   s.pairs = round_up(rows * d.n_bins_max * sizeof(float4));
-  s.geo = round_up((rows * 4 + d.n_chirps_max + d.n_samples_max) * sizeof(float));
+  s.geo = round_up(geo_floats(d) * sizeof(float));
   s.fd = round_up((size_t)d.n_pix_max * sizeof(float));
+  s.pixc = round_up((size_t)d.n_pix_max * sizeof(float4));
+  s.fbase = d.precision == RC_PREC_FP32_SPLIT ? round_up((size_t)d.n_pix_max * sizeof(float)) : 0;
   s.image = round_up((size_t)d.n_pix_max * sizeof(float2));
   s.mask = round_up((size_t)d.n_pix_max * sizeof(unsigned long long));
   s.det_cell = round_up((size_t)d.n_pix_max * sizeof(rc_detection));
@@ -147,8 +158,8 @@ rc_status validate_desc(const rc_plan_desc* d) {
     return fail(RC_EINVAL, "need guard >= 0, train >= 1, guard + train <= 16");
   if (!(d->cfar_pfa > 0 && d->cfar_pfa < 1)) return fail(RC_EINVAL, "cfar_pfa must be in (0, 1)");
   if (d->cfar_margin_rel < 0) return fail(RC_EINVAL, "cfar_margin_rel must be >= 0");
-  if (d->precision != RC_PREC_FP32)
-    return fail(RC_EINVAL, "precision %d is not available in this build", (int)d->precision);
+  if (d->precision != RC_PREC_FP32 && d->precision != RC_PREC_FP32_SPLIT)
+    return fail(RC_EINVAL, "unknown precision %d", (int)d->precision);
   for (rc_window_kind k : {d->range_window, d->sar_window})
     if (k != RC_WIN_RECT && k != RC_WIN_HANN && k != RC_WIN_KAISER)
       return fail(RC_EINVAL, "unknown window kind %d", (int)k);
@@ -239,23 +250,38 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   const int64_t rows = (int64_t)f.n_chirps * f.n_channels;
   const int64_t n_pix = (int64_t)f.n_rows * f.n_cols;
 
-  // geometry staging: rowgeo float4 per (m, ch), then w_sar, then w_range
-  float* g = s.staging;
+  // geometry in aperture-local wavelength units (origin: mean of all antenna
+  // positions) as per-row uniforms (-2 q, |q|^2) for the RX of every (m, ch)
+  // and the TX of every channel group; means and bounding boxes on the way
+  const int chg = tx_group(f);
   double st_x = 0, st_y = 0, sr_x = 0, sr_y = 0;
-  float tlx = INFINITY, tly = INFINITY, thx = -INFINITY, thy = -INFINITY;
-  float rlx = INFINITY, rly = INFINITY, rhx = -INFINITY, rhy = -INFINITY;
   for (int64_t r = 0; r < rows; ++r) {
-    const float tx = f.q_tx[2 * r], ty = f.q_tx[2 * r + 1];
-    const float rx = f.q_rx[2 * r], ry = f.q_rx[2 * r + 1];
+    const double tx = f.q_tx[2 * r], ty = f.q_tx[2 * r + 1];
+    const double rx = f.q_rx[2 * r], ry = f.q_rx[2 * r + 1];
     if (!std::isfinite(tx) || !std::isfinite(ty) || !std::isfinite(rx) || !std::isfinite(ry))
       return fail(RC_EINVAL, "frame %lld: non-finite antenna position", (long long)f.frame_id);
-    g[4 * r + 0] = tx;
-    g[4 * r + 1] = ty;
-    g[4 * r + 2] = rx;
-    g[4 * r + 3] = ry;
     st_x += tx; st_y += ty; sr_x += rx; sr_y += ry;
-    tlx = std::min(tlx, tx); tly = std::min(tly, ty); thx = std::max(thx, tx); thy = std::max(thy, ty);
-    rlx = std::min(rlx, rx); rly = std::min(rly, ry); rhx = std::max(rhx, rx); rhy = std::max(rhy, ry);
+  }
+  const double cen_x = (st_x + sr_x) / (2.0 * rows), cen_y = (st_y + sr_y) / (2.0 * rows);
+  const double lam = c / d.radar.f0, inv_lam = d.radar.f0 / c;
+  float tlx = INFINITY, tly = INFINITY, thx = -INFINITY, thy = -INFINITY;
+  float rlx = INFINITY, rly = INFINITY, rhx = -INFINITY, rhy = -INFINITY;
+  float* g = s.staging;
+  float4* rowq = reinterpret_cast<float4*>(g);
+  float4* grpq = rowq + rows;
+  auto local = [&](const float* q, float& x, float& y) {
+    x = (float)((q[0] - cen_x) * inv_lam);
+    y = (float)((q[1] - cen_y) * inv_lam);
+  };
+  for (int64_t r = 0; r < rows; ++r) {
+    float x, y;
+    local(f.q_rx + 2 * r, x, y);
+    rowq[r] = make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
+    rlx = std::min(rlx, x); rly = std::min(rly, y); rhx = std::max(rhx, x); rhy = std::max(rhy, y);
+    local(f.q_tx + 2 * r, x, y);
+    if (r % chg == 0)
+      grpq[r / chg] = make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
+    tlx = std::min(tlx, x); tly = std::min(tly, y); thx = std::max(thx, x); thy = std::max(thy, y);
   }
   double vx = 0, vy = 0;
   for (int m = 0; m < f.n_chirps; ++m) {
@@ -264,16 +290,17 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   }
   vx /= f.n_chirps;
   vy /= f.n_chirps;
-  float* w_sar = g + 4 * rows;
+  float* w_sar = g + 8 * rows;
   make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
   float* w_range = w_sar + f.n_chirps;
   const int n_s = f.input_kind == RC_INPUT_RAW ? f.n_samples : 0;
   make_window(d.range_window, d.range_kaiser_beta, n_s, w_range);
-  const size_t geo_bytes = (size_t)(4 * rows + f.n_chirps + n_s) * sizeof(float);
+  const size_t geo_bytes = (size_t)(8 * rows + f.n_chirps + n_s) * sizeof(float);
   RC_HIP(hipMemcpyAsync(s.rowgeo, s.staging, geo_bytes, hipMemcpyHostToDevice, st));
-  const float* d_wsar = reinterpret_cast<const float*>(s.rowgeo) + 4 * rows;
+  const float4* d_rowq = s.rowgeo;
+  const float4* d_grpq = s.rowgeo + rows;
+  const float* d_wsar = reinterpret_cast<const float*>(s.rowgeo) + 8 * rows;
   const float* d_wrange = d_wsar + f.n_chirps;
-
   const bool timed = d.stage_timing != 0;
   if (timed) RC_HIP(hipEventRecord(s.stage_ev[0], st));
 
@@ -301,7 +328,7 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
 
   if (timed) RC_HIP(hipEventRecord(s.stage_ev[1], st));
 
-  // 2. Doppler table (Sec. III-D)
+  // 2. per-frame tables: Doppler (Sec. III-D) and local pixel coordinates
   const float2* pix = reinterpret_cast<const float2*>(f.pixels);
   rc::TableArgs ta{};
   ta.pix = pix;
@@ -310,29 +337,36 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   ta.qr_x = sr_x / rows; ta.qr_y = sr_y / rows;
   ta.v_x = vx; ta.v_y = vy;
   ta.kd = kd;
+  ta.c_x = cen_x; ta.c_y = cen_y;
+  ta.inv_lam = inv_lam;
   ta.fd = s.fd;
-  RC_HIP(rc::launch_doppler_table(ta, st));
+  ta.pixc = s.pixc;
+  ta.split = d.precision == RC_PREC_FP32_SPLIT;
+  ta.a1 = a1 * lam;
+  ta.fbase = s.fbase;
+  RC_HIP(rc::launch_pixel_tables(ta, st));
   if (f.doppler_out)
     RC_HIP(hipMemcpyAsync(f.doppler_out, s.fd, n_pix * sizeof(float), hipMemcpyDeviceToDevice, st));
-
   if (timed) RC_HIP(hipEventRecord(s.stage_ev[2], st));
 
   // 3. back-projection (Alg. 2)
   float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
   rc::BpArgs ba{};
-  ba.pix = pix;
+  ba.pixc = s.pixc;
   ba.fd = s.fd;
   ba.pairs = s.pairs;
-  ba.rowgeo = s.rowgeo;
+  ba.rowq = d_rowq;
+  ba.grpq = d_grpq;
   ba.out = img;
+  ba.fbase = s.fbase;
+  ba.split = d.precision == RC_PREC_FP32_SPLIT;
   ba.n_chirps = f.n_chirps;
   ba.n_ch = f.n_channels;
   ba.n_bins = f.n_bins;
-  ba.chg = tx_group(f);
+  ba.chg = chg;
   ba.n_rows = f.n_rows;
   ba.n_cols = f.n_cols;
-  ba.a1 = (float)a1;
-  ba.inv_lam = (float)(d.radar.f0 / c);
+  ba.a1 = (float)(a1 * lam);
   ba.tx_lo_x = tlx; ba.tx_lo_y = tly; ba.tx_hi_x = thx; ba.tx_hi_y = thy;
   ba.rx_lo_x = rlx; ba.rx_lo_y = rly; ba.rx_hi_x = rhx; ba.rx_hi_y = rhy;
   // single-precision error of an index a1 d_hyp + f_doppler <= n_bins is a few
@@ -416,8 +450,7 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     }
   }
   p->slots.resize(desc->max_frames_in_flight);
-  const size_t rows = (size_t)desc->n_chirps_max * desc->n_channels_max;
-  const size_t geo_bytes = (rows * 4 + desc->n_chirps_max + desc->n_samples_max) * sizeof(float);
+  const size_t geo_bytes = geo_floats(*desc) * sizeof(float);
   for (Slot& s : p->slots) {
     char* base = nullptr;
     e = hipMalloc(&base, per_slot);
@@ -431,6 +464,8 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     s.pairs = reinterpret_cast<float4*>(take(sz.pairs));
     s.rowgeo = reinterpret_cast<float4*>(take(sz.geo));
     s.fd = reinterpret_cast<float*>(take(sz.fd));
+    s.pixc = reinterpret_cast<float4*>(take(sz.pixc));
+    s.fbase = sz.fbase ? reinterpret_cast<float*>(take(sz.fbase)) : nullptr;
     s.image = reinterpret_cast<float2*>(take(sz.image));
     s.mask = reinterpret_cast<unsigned long long*>(take(sz.mask));
     s.det_cell = reinterpret_cast<rc_detection*>(take(sz.det_cell));

@@ -6,8 +6,21 @@
 // velocity, and stored in bins:
 //   f_doppler(p) = kd (<p - qt, v>/|p - qt| + <p - qr, v>/|p - qr|),
 // kd = f0 / (c df).  A velocity towards the pixel gives a positive shift.
-// Evaluated in double (the table is O(pixels), the cost is negligible) and
-// rounded once to float.
+//
+// Back-projection works in aperture-local wavelength units P = (p - c) / lambda
+// so that the carrier phase of a path is its length in turns.  The table holds
+// P rounded to float, |P|^2 rounded to float, and the correction (in turns)
+// that restores the rounding of |P|^2 to first order: back-projection forms
+// d^2 = |P|^2 + |q|^2 - 2 P.q, so a rounding delta of |P|^2 shortens each of
+// the two distances of a path by delta / (2 d) ~ delta / (2 |P|).
+// Everything is evaluated in double (O(pixels) work) and rounded once.
+//
+// Split-phase form: a two-way path is written 2R + delta_tx + delta_rx with
+// R = |P| (the path via the aperture centre) and delta = |P - q| - R, a
+// quantity no larger than the antenna's offset from the centre.  The table
+// then holds R and frac(2R) (the reference carrier phase in turns, exact to
+// float rounding) and the index a1 2R + f_doppler of the reference path, so
+// back-projection only ever rounds the small differences.
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -22,7 +35,7 @@ __device__ __forceinline__ double radial(double px, double py, double qx, double
   return d > 0.0 ? (rx * vx + ry * vy) / d : 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void doppler_table_kernel(TableArgs a) {
+__global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= a.n_pix) return;
   const float2 p = a.pix[i];
@@ -30,15 +43,27 @@ __global__ __launch_bounds__(kThreads) void doppler_table_kernel(TableArgs a) {
   const double r = radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y) +
                    radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y);
   a.fd[i] = (float)(a.kd * r);
+  const double lx = (px - a.c_x) * a.inv_lam, ly = (py - a.c_y) * a.inv_lam;
+  const double pp = lx * lx + ly * ly;
+  const float ppf = (float)pp;
+  const double R = sqrt(pp);
+  if (a.split) {
+    const double two_r = 2.0 * R;
+    a.pixc[i] = make_float4((float)lx, (float)ly, (float)R, (float)(two_r - floor(two_r)));
+    a.fbase[i] = (float)(a.a1 * two_r + a.kd * r);
+  } else {
+    const double corr = R > 0.0 ? (pp - (double)ppf) / R : 0.0;
+    a.pixc[i] = make_float4((float)lx, (float)ly, ppf, (float)corr);
+  }
 }
 
 }  // namespace
 
-hipError_t launch_doppler_table(const TableArgs& a, hipStream_t s) {
+hipError_t launch_pixel_tables(const TableArgs& a, hipStream_t s) {
   if (a.n_pix <= 0) return hipSuccess;
   const int64_t grid = (a.n_pix + kThreads - 1) / kThreads;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(doppler_table_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(pixel_tables_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -106,20 +106,39 @@ def small_frame(name="plain-small", **kw):
     return synth.make_frame(cfg)
 
 
-def detection_mismatch(gpu_dets, oracle_cfar, power, n_cols, guard, train, pfa, band):
+def detection_mismatch(gpu_dets, oracle_cfar, power, amp_err, n_cols, guard, train, pfa):
     """Cells on which the GPU and oracle detection lists disagree although the
-    oracle's statistic is farther than ``band`` (relative) from its threshold."""
+    oracle's decision is robust to the image error.
+
+    amp_err[r, c] bounds |P_gpu - P_oracle| at every cell.  A cell's power is
+    then uncertain by 2|P|E + E^2 and its threshold by alpha/N times the sum of
+    that over the training cells; a decision is robust when the oracle's power
+    and threshold are farther apart than the two uncertainties together.
+    Returns (robust cells that disagree, number of disagreeing cells,
+    number of cells whose decision is not robust)."""
     g = set(int(x) for x in gpu_dets["pixel"])
     o = set(int(x) for x in oracle_cfar[0])
     diff = g ^ o
     h = guard + train
     n_train = (2 * h + 1) ** 2 - (2 * guard + 1) ** 2
     alpha = O.cfar_alpha(n_train, pfa)
+    dpow = 2.0 * np.sqrt(power) * amp_err + amp_err ** 2
+    R, C = power.shape
+    view = np.lib.stride_tricks.sliding_window_view
+
+    def train_sum(x):
+        outer = view(x, (2 * h + 1, 2 * h + 1)).sum(axis=(-1, -2))
+        inner = view(x, (2 * guard + 1, 2 * guard + 1)).sum(axis=(-1, -2))
+        off = h - guard
+        return outer - inner[off:off + R - 2 * h, off:off + C - 2 * h]
+
+    thr = alpha * train_sum(power) / n_train
+    dthr = alpha * train_sum(dpow) / n_train
+    cell_p = power[h:R - h, h:C - h]
+    fragile = np.abs(cell_p - thr) <= dpow[h:R - h, h:C - h] + dthr
     bad = []
     for cell in diff:
         r, c = divmod(cell, n_cols)
-        win = power[r - h:r + h + 1, c - h:c + h + 1].sum() - power[r - guard:r + guard + 1, c - guard:c + guard + 1].sum()
-        thr = alpha * win / n_train
-        if abs(power[r, c] - thr) > band * thr:
-            bad.append((cell, float(power[r, c]), float(thr)))
-    return bad, len(diff)
+        if not fragile[r - h, c - h]:
+            bad.append((cell, float(power[r, c]), float(thr[r - h, c - h])))
+    return bad, len(diff), int(fragile.sum())
