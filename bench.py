@@ -98,6 +98,75 @@ def cpu_baseline(frame, budget_s: float = 20.0):
     }
 
 
+def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup):
+    """Times `steps` frames through rc_process_batch + rc_detections on one stream."""
+    dev = torch.device("cuda:0")
+    cfg = frame.cfg
+    raw = torch.from_numpy(frame.raw).to(dev)
+    pix = torch.from_numpy(np.ascontiguousarray(pix_host)).to(dev)
+    n_pix = n_rows * n_cols
+    img = torch.empty((n_pix, 2), dtype=torch.float32, device=dev)
+    pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
+                       n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
+                       n_pix_max=n_pix, max_frames_in_flight=2, max_detections=1 << 16,
+                       precision=precision, stage_timing=True)
+    stream = torch.cuda.current_stream()
+    lat, stages, n_det = [], [], 0
+    with rc.Plan(pc) as plan:
+        def step(fid):
+            fr = rc.Plan.make_frame(fid, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
+                                    n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins, n_fft=frame.n_fft,
+                                    fs=frame.fs, n_samples=cfg.n_samples, image_out=img)
+            plan.process([fr], stream)
+            return plan.detections(fid)
+
+        for i in range(warmup):
+            step(i)
+            plan.release(i)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for i in range(steps):
+            fid = 1000 + i
+            t0 = time.perf_counter()
+            dets = step(fid)
+            lat.append(time.perf_counter() - t0)
+            stages.append(plan.stage_times(fid))
+            plan.release(fid)
+            n_det = len(dets)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+    return {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
+
+
+def paper_config(rc, synth, torch, steps):
+    """The paper's combined setting (Sec. IV, Tab. II rows 7-8): 1024 chirps x
+    8 RX, 30 m x 30 m scene on the polar grid of Sec. III-E, synthetic data."""
+    cfg = synth.CONFIGS["paper-polar"]
+    frame = synth.make_frame(cfg, device="cuda")
+    q = np.concatenate([frame.q_tx.reshape(-1, 2), frame.q_rx.reshape(-1, 2)])
+    L = float(np.ptp(q[:, 0]))
+    g = rc.grid_polar_params(synth.RADAR, cfg.box, (float(q[:, 0].mean()), float(q[:, 1].mean())), L)
+    pix = rc.grid_polar(g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"])
+    x0, x1, y0, y1 = cfg.box
+    in_box = int(np.sum((pix[:, 0] >= x0) & (pix[:, 0] <= x1) & (pix[:, 1] >= y0) & (pix[:, 1] <= y1)))
+    run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, steps, 1)
+    n_pix = g["nth"] * g["nr"]
+    terms = float(n_pix) * cfg.n_chirps * cfg.n_channels
+    bp_ms = float(run["stages"][:, 2].mean())
+    return {
+        "workload": (f"paper-polar: {cfg.n_samples} samples x {cfg.n_chirps} chirps x {cfg.n_channels} RX, polar "
+                     f"lattice {g['nth']} x {g['nr']} (dr {g['dr'] * 100:.2f} cm, dth {g['dth'] * 1e3:.2f} mrad, "
+                     f"aperture {L:.3f} m; {in_box} pixels inside the 30 m x 30 m box)"),
+        "frames_per_s": run["fps"],
+        "ms_per_frame": 1e3 / run["fps"],
+        "backprojection_ms": bp_ms,
+        "bp_terms_per_s": terms / (bp_ms * 1e-3),
+        "p99_ms": 1e3 * float(np.percentile(run["lat"], 99)),
+        "paper_tab2_row8": {"gpu": "GTX 1080 Ti (FP32, pyCUDA)", "bp_ms": 15.5, "total_ms": 18.8,
+                            "bp_terms": 165061 * 1024 * 8, "bp_terms_per_s": 165061 * 1024 * 8 / 15.5e-3},
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +174,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain-large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="skip the split-phase and paper-configuration runs")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for HBM counter calibration)")
@@ -136,44 +207,10 @@ def main(argv=None):
     t0 = time.perf_counter()
     frame = synth.make_frame(cfg, device="cuda")
     t_synth = time.perf_counter() - t0
-    dev = torch.device("cuda:0")
-    raw = torch.from_numpy(frame.raw).to(dev)
-    pix = torch.from_numpy(frame.pix).to(dev)
+    main_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
+                             rc.RC_PREC_FP32, args.steps, args.warmup)
+    stages = main_run["stages"]
     n_pix = frame.n_rows * frame.n_cols
-    img = torch.empty((n_pix, 2), dtype=torch.float32, device=dev)
-    pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
-                       n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
-                       n_pix_max=n_pix, max_frames_in_flight=2, max_detections=1 << 16,
-                       stage_timing=True)
-    plan = rc.Plan(pc)
-    stream = torch.cuda.current_stream()
-
-    def step(fid):
-        fr = rc.Plan.make_frame(fid, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
-                                n_rows=frame.n_rows, n_cols=frame.n_cols, n_bins=frame.n_bins,
-                                n_fft=frame.n_fft, fs=frame.fs, n_samples=cfg.n_samples, image_out=img)
-        plan.process([fr], stream)
-        dets = plan.detections(fid)
-        return dets
-
-    for i in range(args.warmup):
-        step(i)
-        plan.release(i)
-    torch.cuda.synchronize()
-    lat, stages, n_det = [], [], 0
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        fid = 1000 + i
-        t0 = time.perf_counter()
-        dets = step(fid)
-        lat.append(time.perf_counter() - t0)
-        stages.append(plan.stage_times(fid))
-        plan.release(fid)
-        n_det = len(dets)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    stages = np.array(stages)
-    plan.close()
 
     M, CH = cfg.n_chirps, cfg.n_channels
     contrib = float(n_pix) * M * CH
@@ -184,6 +221,8 @@ def main(argv=None):
     peak = VALU_LANE_OPS / slots * flops / 1e12
     range_bytes = float(M * CH) * (8 * cfg.n_samples + 8 * frame.n_bins)
     range_ms = float(stages[:, 0].mean())
+    total = main_run["total_s"]
+    lat = main_run["lat"]
     out = {
         "metric": METRIC,
         "value": args.steps / total,
@@ -211,7 +250,7 @@ def main(argv=None):
         "bp_terms_per_s": contrib / (bp_ms * 1e-3),
         "range_hbm_gbs": range_bytes / (range_ms * 1e-3) / 1e9,
         "range_hbm_frac": range_bytes / (range_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "detections": n_det,
+        "detections": main_run["n_det"],
         "roofline": {
             "bound": "alu",
             "kernel": "bp_kernel (Alg. 2 back-projection)",
@@ -223,6 +262,14 @@ def main(argv=None):
         },
         "synth_s": t_synth,
     }
+    if not args.main_only:
+        # the same frame with the split-phase (high-accuracy) form
+        sp = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
+                           rc.RC_PREC_FP32_SPLIT, max(5, args.steps // 2), 1)
+        out["split_phase_form"] = {
+            "frames_per_s": sp["fps"], "backprojection_ms": float(sp["stages"][:, 2].mean()),
+            "p99_ms": 1e3 * float(np.percentile(sp["lat"], 99))}
+        out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_budget)
     print(json.dumps(out), flush=True)
