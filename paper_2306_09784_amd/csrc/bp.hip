@@ -27,6 +27,12 @@
 //    dependency chains of the multiply-accumulates.
 // A wave covers an 8 x 8 pixel block of the lattice so its gathers of one
 // (m, ch) row touch a handful of neighbouring bins.
+//
+// Work distribution: one launch covers a batch of frames; its work items are
+// (frame, chirp block, 16 x 16 tile).  Workgroups are dispatched to the eight
+// XCDs round robin, so workgroup w is given item (w % 8) * ceil(n / 8) + w / 8:
+// each XCD walks a contiguous range of items, i.e. neighbouring tiles of one
+// chirp block, whose gathers hit the same table rows in that XCD's L2.
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -41,17 +47,16 @@ constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 
 // delta (|delta| <= |q|) and the reference phase frac(2R) enter the phase, so
 // its rounding error scales with the aperture size, not with the range.
 template <int CHG, bool CHECKED>
-__device__ __forceinline__ void bp_terms_split(const BpArgs& a, const float4 p, const float fb,
-                                               float& out_re, float& out_im) {
+__device__ __forceinline__ void bp_terms_split(const BpFrame& a, int row_begin, int row_end, const float4 p,
+                                               const float fb, float& out_re, float& out_im) {
   const float nbm1 = (float)(a.n_bins - 1);
   const int row_bytes = a.n_bins * 16;
-  const int rows = a.n_chirps * a.n_ch;
   const size_t gstride = (size_t)CHG * a.n_bins;
-  const float4* rq = a.rowq;
-  const float4* gq = a.grpq;
-  const float4* tab = a.pairs;
+  const float4* rq = a.rowq + row_begin;
+  const float4* gq = a.grpq + row_begin / CHG;
+  const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  for (int row0 = 0; row0 < rows; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
+  for (int row0 = row_begin; row0 < row_end; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
     const float4 t = gq[0];
     const float nt = fmaf(t.x, p.x, fmaf(t.y, p.y, t.z));
     const float dlt_tx = nt * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, nt)) + p.z);
@@ -97,17 +102,16 @@ __device__ __forceinline__ void bp_terms_split(const BpArgs& a, const float4 p, 
 }
 
 template <int CHG, bool CHECKED>
-__device__ __forceinline__ void bp_terms(const BpArgs& a, const float4 p, const float fdp,
-                                         float& out_re, float& out_im) {
+__device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int row_end, const float4 p,
+                                         const float fdp, float& out_re, float& out_im) {
   const float nbm1 = (float)(a.n_bins - 1);
   const int row_bytes = a.n_bins * 16;
-  const int rows = a.n_chirps * a.n_ch;
   const size_t gstride = (size_t)CHG * a.n_bins;
-  const float4* rq = a.rowq;
-  const float4* gq = a.grpq;
-  const float4* tab = a.pairs;
+  const float4* rq = a.rowq + row_begin;
+  const float4* gq = a.grpq + row_begin / CHG;
+  const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  for (int row0 = 0; row0 < rows; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
+  for (int row0 = row_begin; row0 < row_end; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
     const float4 t = gq[0];
     const float d_tx = __builtin_amdgcn_sqrtf(fmaf(t.x, p.x, fmaf(t.y, p.y, p.z)) + t.z) + p.w;
 #pragma unroll
@@ -163,16 +167,35 @@ __device__ __forceinline__ float box_max_dist(float px, float py, float lx, floa
 }
 
 template <int CHG, bool SPLIT>
-__global__ __launch_bounds__(kThreads) void bp_kernel(BpArgs a) {
+__global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
+  const int w = blockIdx.x;
+  const int per = (b.n_items + 7) >> 3;
+  const int slot = w >> 3;
+  const int item = (w & 7) * per + slot;
+  if (slot >= per || item >= b.n_items) return;
+  int fi = 0;
+  while (fi + 1 < b.n_frames && item >= b.f[fi + 1].item_base) ++fi;
+  // a by-value copy read before any lane-dependent branch keeps every
+  // descriptor field in scalar registers
+  const BpFrame a = b.f[__builtin_amdgcn_readfirstlane(fi)];
+  // the integer divisions below run on the VALU; readfirstlane hands their
+  // (workgroup-uniform) results back to scalar registers so that the table
+  // descriptors derived from them stay scalar
+  const int local = item - a.item_base;
+  const int kb = __builtin_amdgcn_readfirstlane(local / a.n_tiles);
+  const int tile = local - kb * a.n_tiles;
+  const int ty = __builtin_amdgcn_readfirstlane(tile / a.tiles_x);
+  const int tx = tile - ty * a.tiles_x;
+
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int r, c;
   if (a.n_rows >= 8) {  // 16 x 16 workgroup tile of four 8 x 8 wave blocks
-    r = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-    c = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    r = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    c = tx * 16 + (wave & 1) * 8 + (lane & 7);
   } else {              // 1 x 256 workgroup tile of four 1 x 64 wave rows
-    r = blockIdx.y;
-    c = blockIdx.x * kThreads + threadIdx.x;
+    r = ty;
+    c = tx * kThreads + threadIdx.x;
   }
   const bool live = r < a.n_rows && c < a.n_cols;
   // lanes outside the lattice replay its last pixel and store nothing, so the
@@ -181,62 +204,125 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpArgs a) {
   const int cc = c < a.n_cols ? c : a.n_cols - 1;
   const int64_t idx = (int64_t)rr * a.n_cols + cc;
   const float4 p = a.pixc[idx];
-  // plain form: f_doppler; split form: index of the reference path 2R, from
-  // which f_doppler follows for the range bound
-  const float fdp = SPLIT ? a.fbase[idx] - a.a1 * 2.f * p.z : a.fd[idx];
+  const float fi_p = a.fidx[idx];
+  // f_doppler of the pixel (split form: from the index of the reference path)
+  const float fdp = SPLIT ? fi_p - a.a1 * 2.f * p.z : fi_p;
 
   const float dlo = box_min_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
                     box_min_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
   const float dhi = box_max_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
                     box_max_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
   const float flo = fmaf(a.a1, dlo, fdp), fhi = fmaf(a.a1, dhi, fdp);
-  const bool inside = flo >= a.f_margin && fhi <= (float)(a.n_bins - 1) - a.f_margin;
+  const bool inside = (flo >= a.f_margin) & (fhi <= (float)(a.n_bins - 1) - a.f_margin);
+
+  // chirp block kb covers chirps [m0, m1), i.e. rows [m0 n_ch, m1 n_ch)
+  const int m0 = __builtin_amdgcn_readfirstlane((int)(((int64_t)kb * a.n_chirps) / a.n_kb));
+  const int m1 = __builtin_amdgcn_readfirstlane((int)(((int64_t)(kb + 1) * a.n_chirps) / a.n_kb));
+  const int row_begin = m0 * a.n_ch, row_end = m1 * a.n_ch;
 
   float re, im;
   if (SPLIT) {
-    const float fb = a.fbase[idx];
     if (__all(inside))
-      bp_terms_split<CHG, false>(a, p, fb, re, im);
+      bp_terms_split<CHG, false>(a, row_begin, row_end, p, fi_p, re, im);
     else
-      bp_terms_split<CHG, true>(a, p, fb, re, im);
+      bp_terms_split<CHG, true>(a, row_begin, row_end, p, fi_p, re, im);
   } else {
     if (__all(inside))
-      bp_terms<CHG, false>(a, p, fdp, re, im);
+      bp_terms<CHG, false>(a, row_begin, row_end, p, fdp, re, im);
     else
-      bp_terms<CHG, true>(a, p, fdp, re, im);
+      bp_terms<CHG, true>(a, row_begin, row_end, p, fdp, re, im);
   }
-  if (live) a.out[idx] = make_float2(re, im);
+  if (live) a.out[(int64_t)kb * a.n_rows * a.n_cols + idx] = make_float2(re, im);
+}
+
+// Sum of the chirp-block partial images in block order.
+__global__ __launch_bounds__(kThreads) void reduce_partials_kernel(ReduceBatch b) {
+  const ReduceFrame& f = b.f[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < f.n_pix;
+       i += (int64_t)gridDim.x * kThreads) {
+    float re = 0.f, im = 0.f;
+    for (int k = 0; k < f.n_kb; ++k) {
+      const float2 v = f.partial[(int64_t)k * f.n_pix + i];
+      re += v.x;
+      im += v.y;
+    }
+    f.out[i] = make_float2(re, im);
+  }
 }
 
 template <int CHG>
-void launch_chg(const BpArgs& a, dim3 grid, hipStream_t s) {
-  if (a.split)
-    hipLaunchKernelGGL((bp_kernel<CHG, true>), grid, dim3(kThreads), 0, s, a);
+void launch_chg(const BpBatch& b, dim3 grid, hipStream_t s) {
+  if (b.split)
+    hipLaunchKernelGGL((bp_kernel<CHG, true>), grid, dim3(kThreads), 0, s, b);
   else
-    hipLaunchKernelGGL((bp_kernel<CHG, false>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((bp_kernel<CHG, false>), grid, dim3(kThreads), 0, s, b);
 }
 
 }  // namespace
 
-hipError_t launch_backproject(const BpArgs& a, hipStream_t s) {
-  if (a.n_rows <= 0 || a.n_cols <= 0) return hipSuccess;
-  if (a.n_chirps < 1 || a.n_ch < 1 || a.n_bins < 2 || a.chg < 1 || a.n_ch % a.chg != 0 ||
-      (a.split && !a.fbase) ||
-      (int64_t)a.n_bins * 16 >= (int64_t)1 << 31 || (int64_t)a.n_chirps * a.n_ch >= (int64_t)1 << 31)
-    return hipErrorInvalidValue;
-  dim3 grid;
-  if (a.n_rows >= 8)
-    grid = dim3((a.n_cols + 15) / 16, (a.n_rows + 15) / 16);
-  else
-    grid = dim3((a.n_cols + kThreads - 1) / kThreads, a.n_rows);
-  switch (a.chg) {
-    case 16: launch_chg<16>(a, grid, s); break;
-    case 8: launch_chg<8>(a, grid, s); break;
-    case 4: launch_chg<4>(a, grid, s); break;
-    case 2: launch_chg<2>(a, grid, s); break;
-    case 1: launch_chg<1>(a, grid, s); break;
+void bp_tiles(int n_rows, int n_cols, int* tiles_x, int* n_tiles) {
+  if (n_rows >= 8) {
+    *tiles_x = (n_cols + 15) / 16;
+    *n_tiles = *tiles_x * ((n_rows + 15) / 16);
+  } else {
+    *tiles_x = (n_cols + kThreads - 1) / kThreads;
+    *n_tiles = *tiles_x * n_rows;
+  }
+}
+
+int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps) {
+  // 256 CUs x 4 SIMDs x 8 waves = 8192 resident waves; aim at two full
+  // generations of waves, at most 16 blocks and at least one chirp per block
+  int tx, nt;
+  bp_tiles((int)n_rows, (int)n_cols, &tx, &nt);
+  const int64_t waves = (int64_t)nt * (kThreads / 64);
+  int64_t k = (16384 + waves - 1) / waves;
+  if (k > 16) k = 16;
+  if (k > n_chirps) k = n_chirps;
+  return k < 1 ? 1 : (int)k;
+}
+
+hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
+  if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_items < 1 || b.chg < 1) return hipErrorInvalidValue;
+  int items = 0;
+  for (int i = 0; i < b.n_frames; ++i) {
+    const BpFrame& f = b.f[i];
+    int tx, nt;
+    bp_tiles(f.n_rows, f.n_cols, &tx, &nt);
+    if (f.n_rows < 1 || f.n_cols < 1 || f.n_chirps < 1 || f.n_ch < 1 || f.n_bins < 2 || f.n_ch % b.chg != 0 ||
+        f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.item_base != items ||
+        (f.n_rows >= 8 && (f.n_rows + 15) / 16 > 0x7fffffff / 16) ||
+        (int64_t)f.n_bins * 16 >= (int64_t)1 << 31 || (int64_t)f.n_chirps * f.n_ch >= (int64_t)1 << 31)
+      return hipErrorInvalidValue;
+    items += f.n_kb * nt;
+  }
+  if (items != b.n_items) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t)((b.n_items + 7) / 8) * 8;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+  switch (b.chg) {
+    case 16: launch_chg<16>(b, grid, s); break;
+    case 8: launch_chg<8>(b, grid, s); break;
+    case 4: launch_chg<4>(b, grid, s); break;
+    case 2: launch_chg<2>(b, grid, s); break;
+    case 1: launch_chg<1>(b, grid, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const ReduceBatch& b, hipStream_t s) {
+  if (b.n_frames < 0 || b.n_frames > kReduceMaxFrames) return hipErrorInvalidValue;
+  if (b.n_frames == 0) return hipSuccess;
+  int64_t most = 0;
+  for (int i = 0; i < b.n_frames; ++i) {
+    if (b.f[i].n_kb < 1 || b.f[i].n_pix < 0) return hipErrorInvalidValue;
+    most = b.f[i].n_pix > most ? b.f[i].n_pix : most;
+  }
+  int64_t bx = (most + kThreads - 1) / kThreads;
+  if (bx > 4096) bx = 4096;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)bx, b.n_frames), dim3(kThreads), 0, s, b);
   return hipGetLastError();
 }
 

@@ -69,18 +69,25 @@ hipError_t launch_pixel_tables(const TableArgs& a, hipStream_t s);
 // TX position in every chirp form groups of chg channels whose d_tx is
 // evaluated once.  Distances are in wavelengths (a path of d_hyp wavelengths
 // has the carrier phase -2 pi d_hyp), squared distances are formed as
-// pp + |q|^2 - 2 P.q from per-row uniforms.
-struct BpArgs {
-  const float4* pixc;     // [n_rows * n_cols]: (P.x, P.y, |P|^2, corr), wavelengths
-  const float* fd;        // [n_rows * n_cols], bins
+// |P|^2 + |q|^2 - 2 P.q from per-row uniforms.
+//
+// A launch processes a batch of frames that share chg and the precision form.
+// Work items are (frame, chirp block, 16 x 16 pixel tile); a frame too small
+// to fill the GPU splits its chirp sum into n_kb blocks whose partial images
+// are summed afterwards in block order (reduce_partials), so every frame's
+// result depends only on its own sizes, never on the rest of the batch.
+struct BpFrame {
+  const float4* pixc;     // [n_pix]: (P.x, P.y, |P|^2, corr) or split (P.x, P.y, R, frac 2R)
+  const float* fidx;      // [n_pix]: f_doppler (plain) or index of the path 2R (split)
   const float4* pairs;    // [n_chirps * n_ch][n_bins]
   const float4* rowq;     // [n_chirps * n_ch]: (-2 q_rx.x, -2 q_rx.y, |q_rx|^2, 0)
   const float4* grpq;     // [n_chirps * n_ch / chg]: (-2 q_tx.x, -2 q_tx.y, |q_tx|^2, 0)
-  float2* out;            // [n_rows * n_cols]
-  const float* fbase;     // split form: [n_rows * n_cols] index of the reference path
-  int split;              // 0: plain single precision; 1: split phase (see tables)
-  int n_chirps, n_ch, n_bins, chg;
+  float2* out;            // [n_kb][n_pix]: image (n_kb == 1) or partial images
+  int n_chirps, n_ch, n_bins;
   int n_rows, n_cols;
+  int n_kb;               // chirp blocks
+  int tiles_x, n_tiles;   // workgroup tiles per chirp block
+  int item_base;          // first work item of this frame in the launch
   float a1;               // bins per wavelength of two-way path
   // bounding boxes of all TX / RX positions (wavelengths, local frame) and
   // the index margin that lets a wave skip the per-term range test when every
@@ -89,7 +96,33 @@ struct BpArgs {
   float rx_lo_x, rx_lo_y, rx_hi_x, rx_hi_y;
   float f_margin;
 };
-hipError_t launch_backproject(const BpArgs& a, hipStream_t s);
+
+constexpr int kBpMaxFrames = 16;  // frames per launch (descriptors travel as kernel arguments)
+
+struct BpBatch {
+  int chg, split, n_frames, n_items;
+  BpFrame f[kBpMaxFrames];
+};
+hipError_t launch_backproject(const BpBatch& b, hipStream_t s);
+
+// Chirp blocks a frame of n_pix pixels and n_chirps chirps is split into, so
+// that a launch of it alone has enough waves to fill the GPU.
+int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps);
+// Number of work items (workgroups) of one chirp block of a frame.
+void bp_tiles(int n_rows, int n_cols, int* tiles_x, int* n_tiles);
+
+struct ReduceFrame {
+  const float2* partial;  // [n_kb][n_pix]
+  float2* out;            // [n_pix]
+  int64_t n_pix;
+  int n_kb;
+};
+constexpr int kReduceMaxFrames = 32;
+struct ReduceBatch {
+  int n_frames;
+  ReduceFrame f[kReduceMaxFrames];
+};
+hipError_t launch_reduce_partials(const ReduceBatch& b, hipStream_t s);
 
 // 2-D CA-CFAR on |P|^2 (double) over the lattice.  mask holds one 64-bit word
 // per 64 columns of a row; det_cell receives the record of every detection at

@@ -80,6 +80,8 @@ struct Slot {
   float* fd = nullptr;
   float4* pixc = nullptr;
   float* fbase = nullptr;
+  float2* partials = nullptr;
+  int64_t partial_cap = 0;   // pixels x chirp blocks the partial buffer holds
   float2* image = nullptr;
   unsigned long long* mask = nullptr;
   rc_detection* det_cell = nullptr;
@@ -108,11 +110,20 @@ struct Plan {
 };
 
 struct SlotSizes {
-  size_t pairs, geo, fd, pixc, fbase, image, mask, det_cell, det_out;
-  size_t total() const { return pairs + geo + fd + pixc + fbase + image + mask + det_cell + det_out + 64; }
+  size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out;
+  size_t total() const {
+    return pairs + geo + fd + pixc + fbase + partials + image + mask + det_cell + det_out + 64;
+  }
 };
 
 size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Pixel-blocks of partial images a slot may need: a frame is split into n_kb
+// chirp blocks only while it has fewer than 16384 waves (64 pixels each), so
+// n_kb * n_pix < 2^20 + n_pix; never more than 16 blocks.
+int64_t partial_capacity(const rc_plan_desc& d) {
+  return std::min<int64_t>(16 * d.n_pix_max, (int64_t(1) << 20) + d.n_pix_max);
+}
 
 // staging/device geometry region: rowq[rows] and grpq[rows] float4, then
 // w_sar[n_chirps_max] and w_range[n_samples_max]
@@ -129,6 +140,7 @@ SlotSizes slot_sizes(const rc_plan_desc& d) {
   s.fd = round_up((size_t)d.n_pix_max * sizeof(float));
   s.pixc = round_up((size_t)d.n_pix_max * sizeof(float4));
   s.fbase = d.precision == RC_PREC_FP32_SPLIT ? round_up((size_t)d.n_pix_max * sizeof(float)) : 0;
+  s.partials = round_up((size_t)partial_capacity(d) * sizeof(float2));
   s.image = round_up((size_t)d.n_pix_max * sizeof(float2));
   s.mask = round_up((size_t)d.n_pix_max * sizeof(unsigned long long));
   s.det_cell = round_up((size_t)d.n_pix_max * sizeof(rc_detection));
@@ -204,6 +216,16 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
   if (!(f.fs > 0)) return fail(RC_EINVAL, "frame %lld: fs must be positive", (long long)f.frame_id);
   if (!f.data || !f.q_tx || !f.q_rx || !f.vel || !f.pixels)
     return fail(RC_EINVAL, "frame %lld: data, q_tx, q_rx, vel and pixels are required", (long long)f.frame_id);
+  const int64_t rows = (int64_t)f.n_chirps * f.n_channels;
+  for (int64_t i = 0; i < 2 * rows; ++i)
+    if (!std::isfinite(f.q_tx[i]) || !std::isfinite(f.q_rx[i]))
+      return fail(RC_EINVAL, "frame %lld: non-finite antenna position", (long long)f.frame_id);
+  for (int64_t i = 0; i < 2 * (int64_t)f.n_chirps; ++i)
+    if (!std::isfinite(f.vel[i]))
+      return fail(RC_EINVAL, "frame %lld: non-finite velocity", (long long)f.frame_id);
+  const int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps);
+  if (n_kb > 1 && (int64_t)n_kb * f.n_rows * f.n_cols > partial_capacity(d))
+    return fail(RC_EINVAL, "frame %lld: %d chirp blocks exceed the partial-image buffer", (long long)f.frame_id, n_kb);
   if (f.input_kind == RC_INPUT_RAW) {
     if (f.n_samples < 1 || f.n_samples > d.n_samples_max)
       return fail(RC_EINVAL, "frame %lld: n_samples %d outside [1, %d]", (long long)f.frame_id, f.n_samples, d.n_samples_max);
@@ -240,7 +262,10 @@ int tx_group(const rc_frame& f) {
   return 1;
 }
 
-rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
+// Steps 1-2 of a frame (geometry upload, range compression, pixel tables) and
+// its back-projection descriptor; the batch launches back-projection for all
+// its frames at once (finish_frame then runs detection and the read-back).
+rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc::BpFrame* bf, int* chg_out) {
   const rc_plan_desc& d = p->d;
   const double c = d.radar.c > 0 ? d.radar.c : 299792458.0;
   const double mu = d.radar.bandwidth / d.radar.t_chirp;
@@ -258,8 +283,6 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   for (int64_t r = 0; r < rows; ++r) {
     const double tx = f.q_tx[2 * r], ty = f.q_tx[2 * r + 1];
     const double rx = f.q_rx[2 * r], ry = f.q_rx[2 * r + 1];
-    if (!std::isfinite(tx) || !std::isfinite(ty) || !std::isfinite(rx) || !std::isfinite(ry))
-      return fail(RC_EINVAL, "frame %lld: non-finite antenna position", (long long)f.frame_id);
     st_x += tx; st_y += ty; sr_x += rx; sr_y += ry;
   }
   const double cen_x = (st_x + sr_x) / (2.0 * rows), cen_y = (st_y + sr_y) / (2.0 * rows);
@@ -347,34 +370,49 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   RC_HIP(rc::launch_pixel_tables(ta, st));
   if (f.doppler_out)
     RC_HIP(hipMemcpyAsync(f.doppler_out, s.fd, n_pix * sizeof(float), hipMemcpyDeviceToDevice, st));
-  if (timed) RC_HIP(hipEventRecord(s.stage_ev[2], st));
 
-  // 3. back-projection (Alg. 2)
+  // back-projection descriptor (Alg. 2), launched batch-wide by the caller
   float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
-  rc::BpArgs ba{};
+  const int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps);
+  rc::BpFrame& ba = *bf;
+  ba = rc::BpFrame{};
   ba.pixc = s.pixc;
-  ba.fd = s.fd;
+  ba.fidx = d.precision == RC_PREC_FP32_SPLIT ? s.fbase : s.fd;
   ba.pairs = s.pairs;
   ba.rowq = d_rowq;
   ba.grpq = d_grpq;
-  ba.out = img;
-  ba.fbase = s.fbase;
-  ba.split = d.precision == RC_PREC_FP32_SPLIT;
+  ba.out = n_kb > 1 ? s.partials : img;
   ba.n_chirps = f.n_chirps;
   ba.n_ch = f.n_channels;
   ba.n_bins = f.n_bins;
-  ba.chg = chg;
   ba.n_rows = f.n_rows;
   ba.n_cols = f.n_cols;
+  ba.n_kb = n_kb;
+  rc::bp_tiles(f.n_rows, f.n_cols, &ba.tiles_x, &ba.n_tiles);
   ba.a1 = (float)(a1 * lam);
   ba.tx_lo_x = tlx; ba.tx_lo_y = tly; ba.tx_hi_x = thx; ba.tx_hi_y = thy;
   ba.rx_lo_x = rlx; ba.rx_lo_y = rly; ba.rx_hi_x = rhx; ba.rx_hi_y = rhy;
   // single-precision error of an index a1 d_hyp + f_doppler <= n_bins is a few
   // ulps of n_bins; the margin keeps such waves on the range-tested path
   ba.f_margin = (float)(1e-3 + 64.0 * f.n_bins * std::ldexp(1.0, -24));
-  RC_HIP(rc::launch_backproject(ba, st));
-  if (timed) RC_HIP(hipEventRecord(s.stage_ev[3], st));
+  if (n_kb > 1 && (int64_t)n_kb * n_pix > s.partial_cap)
+    return fail(RC_EINVAL, "frame %lld: %d chirp blocks of %lld pixels exceed the slot's partial buffer",
+                (long long)f.frame_id, n_kb, (long long)n_pix);
+  *chg_out = chg;
+  s.busy = true;
+  s.frame_id = f.frame_id;
+  s.n_rows = f.n_rows;
+  s.n_cols = f.n_cols;
+  s.image_used = img;
+  return RC_OK;
+}
 
+// Step 4 of a frame: CA-CFAR, ordered compaction and the asynchronous
+// read-back of the detections; records the frame's completion event.
+rc_status finish_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
+  const rc_plan_desc& d = p->d;
+  const bool timed = d.stage_timing != 0;
+  float2* img = s.image_used;
   // 4. CA-CFAR + ordered compaction, then the asynchronous read-back
   const int h = d.cfar_guard + d.cfar_train;
   const int n_train = (2 * h + 1) * (2 * h + 1) - (2 * d.cfar_guard + 1) * (2 * d.cfar_guard + 1);
@@ -391,12 +429,6 @@ rc_status enqueue_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   const int prefix = std::min(kDetPrefix, d.max_detections);
   RC_HIP(hipMemcpyAsync(s.h_det, s.det_out, prefix * sizeof(rc_detection), hipMemcpyDeviceToHost, st));
   RC_HIP(hipEventRecord(s.done, st));
-
-  s.busy = true;
-  s.frame_id = f.frame_id;
-  s.n_rows = f.n_rows;
-  s.n_cols = f.n_cols;
-  s.image_used = img;
   return RC_OK;
 }
 
@@ -466,6 +498,8 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     s.fd = reinterpret_cast<float*>(take(sz.fd));
     s.pixc = reinterpret_cast<float4*>(take(sz.pixc));
     s.fbase = sz.fbase ? reinterpret_cast<float*>(take(sz.fbase)) : nullptr;
+    s.partials = reinterpret_cast<float2*>(take(sz.partials));
+    s.partial_cap = partial_capacity(*desc);
     s.image = reinterpret_cast<float2*>(take(sz.image));
     s.mask = reinterpret_cast<unsigned long long*>(take(sz.mask));
     s.det_cell = reinterpret_cast<rc_detection*>(take(sz.det_cell));
@@ -509,11 +543,59 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
         return fail(RC_EINVAL, "frame id %lld repeated in the batch", (long long)frames[i].frame_id);
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<Slot*> slot(n_frames, nullptr);
+  std::vector<rc::BpFrame> bpf(n_frames);
+  std::vector<int> chg(n_frames, 1);
+  auto undo = [&](rc_status r) {  // a failed batch leaves no slot busy
+    (void)hipStreamSynchronize(st);
+    for (Slot* q : slot)
+      if (q) { q->busy = false; q->frame_id = -1; }
+    return r;
+  };
+  // 1-2: per-frame geometry, range compression and pixel tables
   for (int i = 0; i < n_frames; ++i) {
-    Slot* s = nullptr;
     for (Slot& c : p->slots)
-      if (!c.busy) { s = &c; break; }
-    rc_status r = enqueue_frame(p, *s, frames[i], st);
+      if (!c.busy) { slot[i] = &c; break; }
+    rc_status r = prepare_frame(p, *slot[i], frames[i], st, &bpf[i], &chg[i]);
+    if (r != RC_OK) return undo(r);
+  }
+  const bool timed = p->d.stage_timing != 0;
+  if (timed)
+    for (Slot* q : slot) RC_HIP(hipEventRecord(q->stage_ev[2], st));
+  // 3: back-projection, one launch per TX-group width and per 16 frames
+  std::vector<char> done(n_frames, 0);
+  for (int i = 0; i < n_frames; ++i) {
+    if (done[i]) continue;
+    rc::BpBatch b{};
+    b.chg = chg[i];
+    b.split = p->d.precision == RC_PREC_FP32_SPLIT;
+    for (int j = i; j < n_frames && b.n_frames < rc::kBpMaxFrames; ++j) {
+      if (done[j] || chg[j] != chg[i]) continue;
+      rc::BpFrame fj = bpf[j];
+      fj.item_base = b.n_items;
+      b.f[b.n_frames++] = fj;
+      b.n_items += fj.n_kb * fj.n_tiles;
+      done[j] = 1;
+    }
+    hipError_t e = rc::launch_backproject(b, st);
+    if (e != hipSuccess) return undo(fail(RC_EHIP, "back-projection launch: %s", hipGetErrorString(e)));
+  }
+  rc::ReduceBatch rb{};
+  for (int i = 0; i < n_frames; ++i) {
+    if (bpf[i].n_kb == 1) continue;
+    rb.f[rb.n_frames++] = rc::ReduceFrame{bpf[i].out, slot[i]->image_used,
+                                          (int64_t)frames[i].n_rows * frames[i].n_cols, bpf[i].n_kb};
+    if (rb.n_frames == rc::kReduceMaxFrames) {
+      RC_HIP(rc::launch_reduce_partials(rb, st));
+      rb.n_frames = 0;
+    }
+  }
+  if (rb.n_frames) RC_HIP(rc::launch_reduce_partials(rb, st));
+  if (timed)
+    for (Slot* q : slot) RC_HIP(hipEventRecord(q->stage_ev[3], st));
+  // 4: detection and read-back per frame
+  for (int i = 0; i < n_frames; ++i) {
+    rc_status r = finish_frame(p, *slot[i], frames[i], st);
     if (r != RC_OK) return r;
   }
   return RC_OK;

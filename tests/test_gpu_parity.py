@@ -262,3 +262,55 @@ def test_abi_errors_on_device(rc, torch):
         plan.release(3)
         plan.process([mk(4)])
         plan.release(4)
+
+
+# ---------------------------------------------------------------------------
+# batches of frames of mixed sizes
+# ---------------------------------------------------------------------------
+def _mixed_frames(n):
+    rng = np.random.default_rng(3000)
+    frames = []
+    for i in range(n):
+        n_tx, n_rx = [(1, 4), (1, 8), (2, 4), (1, 2)][i % 4]
+        shape = [(40, 37), (64, 64), (1, 300), (20, 90), (33, 16)][i % 5]
+        cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name=f"mix{i}",
+                                  n_samples=int(rng.choice([32, 64, 128])),
+                                  n_chirps=int(rng.choice([6, 12, 24])), n_tx=n_tx, n_rx=n_rx,
+                                  nx=shape[1], ny=shape[0], box=(-4.0, 4.0, 1.5, 7.0), n_targets=2,
+                                  seed=3000 + i)
+        frames.append(synth.make_frame(cfg, frame_index=i))
+    return frames
+
+
+@pytest.mark.parametrize("n_frames", [5, 19])
+def test_batch_of_mixed_frames_matches_each_frame_alone(rc, torch, n_frames):
+    """One rc_process_batch call over frames of different sizes, TX groupings
+    and lattices: every image is bitwise identical to the same frame processed
+    alone, and matches the oracle.  19 frames exceed one launch's 16."""
+    frames = _mixed_frames(n_frames)
+    cfg = SC.plan_config(rc, frames, max_frames_in_flight=n_frames)
+    dev = torch.device("cuda")
+    with rc.Plan(cfg) as plan:
+        keep, descs, imgs = [], [], []
+        for i, fr in enumerate(frames):
+            t = SC.to_device(fr, torch)
+            img = torch.empty((fr.n_rows * fr.n_cols, 2), dtype=torch.float32, device=dev)
+            keep.append(t)
+            imgs.append(img)
+            descs.append(rc.Plan.make_frame(100 + i, data=t["raw"], q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel,
+                                            pixels=t["pix"], n_rows=fr.n_rows, n_cols=fr.n_cols,
+                                            n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
+                                            n_samples=fr.cfg.n_samples, image_out=img))
+        plan.process(descs)
+        dets_mix = [plan.detections(100 + i) for i in range(n_frames)]
+        torch.cuda.synchronize()
+        mixed = [im.cpu().numpy().copy() for im in imgs]
+        for i in range(n_frames):
+            plan.release(100 + i)
+        for i, fr in enumerate(frames):
+            alone = SC.run_gpu(rc, plan, fr, torch, frame_id=500 + i)
+            assert np.array_equal(alone["image"].view(np.float32).reshape(-1, 2), mixed[i]), f"frame {i}"
+            assert np.array_equal(alone["detections"], dets_mix[i]), f"frame {i}"
+    for i in (0, n_frames - 1):
+        ora = SC.run_oracle(frames[i], cfar=None)
+        _check_image(f"batch_frame{i}", frames[i], mixed[i].view(np.complex64).reshape(-1), ora, PLAIN)
