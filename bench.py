@@ -167,6 +167,75 @@ def paper_config(rc, synth, torch, steps):
     }
 
 
+def make_sensors(rc, synth, torch, n_sensors, seed=3000):
+    """Mixed-size sensor population (see synth.mixed_configs): one frame per
+    sensor, beat cube in pinned host memory, pixel grid resident on the GPU."""
+    from paper_2306_09784_amd import serve
+
+    sensors = []
+    for i, cfg in enumerate(synth.mixed_configs(n_sensors, seed)):
+        fr = synth.make_frame(cfg, frame_index=i, device="cuda")
+        raw = torch.from_numpy(fr.raw).pin_memory()
+        pix = torch.from_numpy(fr.pix).to("cuda")
+        sensors.append(serve.SensorStream(i, fr, raw, pix))
+    return sensors
+
+
+def mixed_plan_config(rc, synth, sensors, slots, **kw):
+    frs = [s.frame for s in sensors]
+    return rc.PlanConfig(radar=synth.RADAR, n_samples_max=max(f.cfg.n_samples for f in frs),
+                         n_fft_max=max(f.n_fft for f in frs), n_bins_max=max(f.n_bins for f in frs),
+                         n_chirps_max=max(f.cfg.n_chirps for f in frs),
+                         n_channels_max=max(f.cfg.n_channels for f in frs),
+                         n_pix_max=max(f.n_rows * f.n_cols for f in frs), max_frames_in_flight=slots,
+                         max_detections=1 << 14, **kw)
+
+
+def batched_mixed(rc, synth, torch, sensors, n_frames=64, slots=32):
+    """Frames of mixed sizes in batches of `slots` frames per rc_process_batch
+    (one back-projection launch per TX-group width and 16 frames); each batch
+    includes the pinned-memory upload of its beat cubes."""
+    from paper_2306_09784_amd import serve
+
+    srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots), n_streams=1)
+    try:
+        order = [sensors[i % len(sensors)] for i in range(n_frames)]
+        # warm-up batch
+        srv.submit([(10**6 + i, order[i], time.perf_counter()) for i in range(min(slots, n_frames))])
+        srv.harvest(block=True)
+        srv.results.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fid = 1
+        for b0 in range(0, n_frames, slots):
+            items = [(fid + i, order[b0 + i], time.perf_counter()) for i in range(min(slots, n_frames - b0))]
+            fid += len(items)
+            srv.submit(items)
+            srv.harvest(block=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        srv.close()
+    terms = sum(s.frame.n_rows * s.frame.n_cols * s.frame.cfg.n_chirps * s.frame.cfg.n_channels for s in order)
+    return {"frames": n_frames, "batch": slots, "frames_per_s": n_frames / wall,
+            "bp_terms_per_s_incl_all_stages": terms / wall, "wall_s": wall}
+
+
+def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=32):
+    """Poisson arrivals from all sensors at `load` x the measured batch capacity,
+    continuous batching over the plan's slots, two streams."""
+    from paper_2306_09784_amd import serve
+
+    srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots), n_streams=2)
+    try:
+        res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s)
+    finally:
+        srv.close()
+    res["load"] = load
+    res["realtime_bound_ms"] = 1024 * synth.RADAR["t_pri"] * 1e3
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +243,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain-large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="duration of the Poisson serving run (0 disables it)")
     ap.add_argument("--main-only", action="store_true",
                     help="skip the split-phase and paper-configuration runs")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -270,6 +341,11 @@ def main(argv=None):
             "frames_per_s": sp["fps"], "backprojection_ms": float(sp["stages"][:, 2].mean()),
             "p99_ms": 1e3 * float(np.percentile(sp["lat"], 99))}
         out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
+        sensors = make_sensors(rc, synth, torch, 32)
+        out["batched_mixed"] = batched_mixed(rc, synth, torch, sensors)
+        if args.serve_seconds > 0:
+            out["serving"] = serving(rc, synth, torch, sensors, out["batched_mixed"]["frames_per_s"],
+                                     args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_budget)
     print(json.dumps(out), flush=True)

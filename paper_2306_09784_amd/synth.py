@@ -288,3 +288,21 @@ def random_spectrum(rng: np.random.Generator, shape: Sequence[int]) -> np.ndarra
     """complex64 CN(0, 1) array, e.g. a beat spectrum [M, CH, NB] for stage tests."""
     z = rng.standard_normal((2,) + tuple(shape))
     return ((z[0] + 1j * z[1]) * math.sqrt(0.5)).astype(np.complex64)
+
+
+def mixed_configs(n: int, seed: int = 3000):
+    """Scene configurations of a mixed-size sensor population: n_samples in
+    {128, 256, 512, 1024}, n_chirps in {64, 128, 256, 512}, channels in
+    {4, 8, 16} (one TX), a G x G Cartesian grid with G in {128, 256, 512}, all
+    drawn uniformly; 8 point targets at 10-30 dB in a 15 m box, which keeps the
+    farthest path inside the unambiguous range of the smallest sample count."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        g = int(rng.choice([128, 256, 512]))
+        out.append(SceneConfig(
+            f"mixed-{i}", n_samples=int(rng.choice([128, 256, 512, 1024])),
+            n_chirps=int(rng.choice([64, 128, 256, 512])), n_tx=1, n_rx=int(rng.choice([4, 8, 16])),
+            box=(-7.5, 7.5, 1.0, 16.0), nx=g, ny=g, n_targets=8, snr_db=(10.0, 30.0),
+            seed=int(seed + 1 + i)))
+    return out

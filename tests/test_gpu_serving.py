@@ -1,0 +1,96 @@
+"""Continuous batching on the GPU: frames of many sensors arriving at random
+times are admitted into the plan's slots while others are in flight, on two
+streams; every frame's result is the same as the frame processed alone."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2306_09784_amd import synth
+from tests import sar_cases as SC
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def rc():
+    from paper_2306_09784_amd import rc as mod
+
+    return mod
+
+
+def _sensors(torch, n):
+    from paper_2306_09784_amd import serve
+
+    rng = np.random.default_rng(41)
+    out = []
+    for i in range(n):
+        cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name=f"s{i}",
+                                  n_samples=int(rng.choice([32, 64])), n_chirps=int(rng.choice([8, 16])),
+                                  n_rx=int(rng.choice([2, 4, 8])), nx=int(rng.choice([24, 40])),
+                                  ny=int(rng.choice([1, 24, 33])), box=(-4.0, 4.0, 1.5, 7.0), seed=500 + i)
+        fr = synth.make_frame(cfg, frame_index=i)
+        out.append(serve.SensorStream(i, fr, torch.from_numpy(fr.raw).pin_memory(),
+                                      torch.from_numpy(fr.pix).to("cuda")))
+    return out
+
+
+def test_poisson_serving_results_equal_alone(rc, torch):
+    from paper_2306_09784_amd import serve
+
+    sensors = _sensors(torch, 6)
+    cfg = SC.plan_config(rc, [s.frame for s in sensors], max_frames_in_flight=4)
+    srv = serve.Server(cfg, n_streams=2, keep_images=True)
+    peak = [0]
+    orig_submit = srv.submit
+
+    def submit(items):
+        orig_submit(items)
+        peak[0] = max(peak[0], len(srv.inflight))
+
+    srv.submit = submit
+    try:
+        res = serve.run_poisson(srv, sensors, rate_hz=400.0, duration_s=0.5, seed=7)
+        assert res["frames"] == len(srv.results) > 50
+        assert peak[0] <= 4                                   # admission never exceeds the slots
+        assert res["p50_ms"] > 0 and res["p99_ms"] >= res["p50_ms"]
+        by_sensor = {}
+        for r in srv.results:
+            by_sensor.setdefault(r.sensor_id, []).append(r)
+        alone = {}
+        for s in sensors:
+            out = SC.run_gpu(rc, srv.plan, s.frame, torch, frame_id=10**7 + s.sensor_id)
+            alone[s.sensor_id] = out
+        for sid, rs in by_sensor.items():
+            fr = sensors[sid].frame
+            ref = alone[sid]["image"].view(np.float32).reshape(-1, 2)
+            for r in rs[:5]:
+                img = srv.image_of[r.frame_id][: fr.n_rows * fr.n_cols]
+                assert np.array_equal(img, ref), (sid, r.frame_id)
+                assert np.array_equal(r.detections, alone[sid]["detections"]), (sid, r.frame_id)
+    finally:
+        srv.close()
+
+
+def test_burst_waits_for_slots(rc, torch):
+    """A burst larger than the slot count queues; every frame completes."""
+    from paper_2306_09784_amd import serve
+
+    sensors = _sensors(torch, 3)
+    cfg = SC.plan_config(rc, [s.frame for s in sensors], max_frames_in_flight=2)
+    srv = serve.Server(cfg, n_streams=2)
+    try:
+        res = serve.run_poisson(srv, sensors, rate_hz=20000.0, duration_s=0.002, seed=3)
+        assert res["frames"] >= 10
+        assert len(srv.free) == 2 and not srv.inflight
+    finally:
+        srv.close()
