@@ -246,7 +246,9 @@ def main(argv=None):
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the Poisson serving run (0 disables it)")
     ap.add_argument("--main-only", action="store_true",
-                    help="skip the split-phase and paper-configuration runs")
+                    help="skip the split-phase, paper-configuration, batched and serving runs")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the mixed-size batch run (printed as its own JSON line)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for HBM counter calibration)")
@@ -274,6 +276,10 @@ def main(argv=None):
         return 0
     from paper_2306_09784_amd import rc, synth
 
+    if args.batched_only:
+        sensors = make_sensors(rc, synth, torch, 32)
+        print(json.dumps({"batched_mixed": batched_mixed(rc, synth, torch, sensors)}), flush=True)
+        return 0
     cfg = synth.CONFIGS[args.workload]
     t0 = time.perf_counter()
     frame = synth.make_frame(cfg, device="cuda")

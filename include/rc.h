@@ -67,6 +67,16 @@ typedef enum rc_precision {
   RC_PREC_FP32_SPLIT = 1
 } rc_precision;
 
+typedef enum rc_doppler_mode {
+  /* Alg. 2: the Doppler shift of each pixel is evaluated once, at the
+   * aperture centre with the mean velocity (Sec. III-D). */
+  RC_DOPPLER_AVERAGE = 0,
+  /* Alg. 1: the radial velocity of every pixel, chirp and channel from that
+   * chirp's velocity (the paper's reference before the simplification).
+   * Single precision only (not with RC_PREC_FP32_SPLIT). */
+  RC_DOPPLER_EXACT = 1
+} rc_doppler_mode;
+
 typedef enum rc_input_kind {
   RC_INPUT_RAW = 0,      /* data = beat signal complex64 [n_chirps][n_channels][n_samples] */
   RC_INPUT_SPECTRUM = 1  /* data = beat spectrum complex64 [n_chirps][n_channels][n_bins]  */
@@ -95,6 +105,7 @@ typedef struct rc_plan_desc {
   rc_window_kind range_window;  double range_kaiser_beta;
   rc_window_kind sar_window;    double sar_kaiser_beta;   /* w_sar over chirps   */
   rc_precision precision;
+  rc_doppler_mode doppler;
   int32_t cfar_guard;           /* guard cells each side (2)                      */
   int32_t cfar_train;           /* training cells each side beyond guard (8)      */
   double cfar_pfa;              /* design false-alarm probability (1e-4)          */

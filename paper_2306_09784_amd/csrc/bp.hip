@@ -1,4 +1,5 @@
-// Back-projection core: Alg. 2 of the paper (Sec. IV), single precision.
+// Back-projection core: Alg. 2 of the paper (Sec. IV), single precision; the
+// exact-Doppler form evaluates Alg. 1 (Sec. II) for the ablation of Sec. III-D.
 //
 // For every pixel p the lane evaluates, for each chirp m and channel ch,
 //   d_hyp = |p - q_tx(m,ch)| + |p - q_rx(m,ch)|,
@@ -101,6 +102,68 @@ __device__ __forceinline__ void bp_terms_split(const BpFrame& a, int row_begin, 
   out_im = im0 + im1;
 }
 
+// Exact-Doppler form (Alg. 1): each leg also contributes its own Doppler
+// index shift <P - q, kd v(m)> / |P - q| from the chirp's velocity, so the
+// distances need the difference vector and a reciprocal.
+template <int CHG, bool CHECKED>
+__device__ __forceinline__ void bp_terms_exact(const BpFrame& a, int row_begin, int row_end, const float4 p,
+                                               float& out_re, float& out_im) {
+  const float nbm1 = (float)(a.n_bins - 1);
+  const int row_bytes = a.n_bins * 16;
+  const size_t gstride = (size_t)CHG * a.n_bins;
+  const float4* rv = a.rowv + row_begin;
+  const float4* gv = a.grpv + row_begin / CHG;
+  const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
+  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+  for (int row0 = row_begin; row0 < row_end; row0 += CHG, rv += CHG, ++gv, tab += gstride) {
+    const float4 t = gv[0];
+    const float tx = p.x - t.x, ty = p.y - t.y;
+    const float d_tx = __builtin_amdgcn_sqrtf(fmaf(tx, tx, ty * ty));
+    const float dop_tx = fmaf(tx, t.z, ty * t.w) * __builtin_amdgcn_rcpf(d_tx);
+    const float d_tx_c = d_tx + p.w;
+#pragma unroll
+    for (int j = 0; j < CHG; ++j) {
+      const float4 q = rv[j];
+      const float rx = p.x - q.x, ry = p.y - q.y;
+      const float d_rx = __builtin_amdgcn_sqrtf(fmaf(rx, rx, ry * ry));
+      const float dop = dop_tx + fmaf(rx, q.z, ry * q.w) * __builtin_amdgcn_rcpf(d_rx);
+      const float d_hyp = d_tx_c + d_rx;
+      const float f = fmaf(a.a1, d_hyp, dop);
+      int i;
+      float phi;
+      if (CHECKED) {
+        const float fl = floorf(f);
+        phi = f - fl;
+        i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;
+      } else {
+        i = (int)f;
+        phi = __builtin_amdgcn_fractf(f);
+      }
+      const float turn = __builtin_amdgcn_fractf(d_hyp);
+      const float sn = __builtin_amdgcn_sinf(turn);
+      const float cs = __builtin_amdgcn_cosf(turn);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(tab + (size_t)j * a.n_bins), (short)0, row_bytes, kRsrcWord3);
+      const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
+      const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
+      const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
+      if (j & 1) {
+        re1 = fmaf(cs, vr, re1);
+        re1 = fmaf(sn, vi, re1);
+        im1 = fmaf(cs, vi, im1);
+        im1 = fmaf(-sn, vr, im1);
+      } else {
+        re0 = fmaf(cs, vr, re0);
+        re0 = fmaf(sn, vi, re0);
+        im0 = fmaf(cs, vi, im0);
+        im0 = fmaf(-sn, vr, im0);
+      }
+    }
+  }
+  out_re = re0 + re1;
+  out_im = im0 + im1;
+}
+
 template <int CHG, bool CHECKED>
 __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int row_end, const float4 p,
                                          const float fdp, float& out_re, float& out_im) {
@@ -166,8 +229,10 @@ __device__ __forceinline__ float box_max_dist(float px, float py, float lx, floa
   return sqrtf(dx * dx + dy * dy);
 }
 
-template <int CHG, bool SPLIT>
+template <int CHG, int FORM>
 __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
+  constexpr bool SPLIT = FORM == kBpSplit;
+  constexpr bool EXACT = FORM == kBpExact;
   const int w = blockIdx.x;
   const int per = (b.n_items + 7) >> 3;
   const int slot = w >> 3;
@@ -205,15 +270,17 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   const int64_t idx = (int64_t)rr * a.n_cols + cc;
   const float4 p = a.pixc[idx];
   const float fi_p = a.fidx[idx];
-  // f_doppler of the pixel (split form: from the index of the reference path)
-  const float fdp = SPLIT ? fi_p - a.a1 * 2.f * p.z : fi_p;
+  // f_doppler of the pixel (split form: from the index of the reference path;
+  // exact form: per term, bounded by f_slack)
+  const float fdp = EXACT ? 0.f : (SPLIT ? fi_p - a.a1 * 2.f * p.z : fi_p);
 
   const float dlo = box_min_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
                     box_min_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
   const float dhi = box_max_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
                     box_max_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
   const float flo = fmaf(a.a1, dlo, fdp), fhi = fmaf(a.a1, dhi, fdp);
-  const bool inside = (flo >= a.f_margin) & (fhi <= (float)(a.n_bins - 1) - a.f_margin);
+  const float mg = a.f_margin + a.f_slack;
+  const bool inside = (flo >= mg) & (fhi <= (float)(a.n_bins - 1) - mg);
 
   // chirp block kb covers chirps [m0, m1), i.e. rows [m0 n_ch, m1 n_ch)
   const int m0 = __builtin_amdgcn_readfirstlane((int)(((int64_t)kb * a.n_chirps) / a.n_kb));
@@ -221,7 +288,12 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   const int row_begin = m0 * a.n_ch, row_end = m1 * a.n_ch;
 
   float re, im;
-  if (SPLIT) {
+  if (EXACT) {
+    if (__all(inside))
+      bp_terms_exact<CHG, false>(a, row_begin, row_end, p, re, im);
+    else
+      bp_terms_exact<CHG, true>(a, row_begin, row_end, p, re, im);
+  } else if (SPLIT) {
     if (__all(inside))
       bp_terms_split<CHG, false>(a, row_begin, row_end, p, fi_p, re, im);
     else
@@ -252,10 +324,12 @@ __global__ __launch_bounds__(kThreads) void reduce_partials_kernel(ReduceBatch b
 
 template <int CHG>
 void launch_chg(const BpBatch& b, dim3 grid, hipStream_t s) {
-  if (b.split)
-    hipLaunchKernelGGL((bp_kernel<CHG, true>), grid, dim3(kThreads), 0, s, b);
+  if (b.form == kBpSplit)
+    hipLaunchKernelGGL((bp_kernel<CHG, kBpSplit>), grid, dim3(kThreads), 0, s, b);
+  else if (b.form == kBpExact)
+    hipLaunchKernelGGL((bp_kernel<CHG, kBpExact>), grid, dim3(kThreads), 0, s, b);
   else
-    hipLaunchKernelGGL((bp_kernel<CHG, false>), grid, dim3(kThreads), 0, s, b);
+    hipLaunchKernelGGL((bp_kernel<CHG, kBpPlain>), grid, dim3(kThreads), 0, s, b);
 }
 
 }  // namespace
@@ -283,13 +357,16 @@ int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps) {
 }
 
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
-  if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_items < 1 || b.chg < 1) return hipErrorInvalidValue;
+  if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_items < 1 || b.chg < 1 || b.form < kBpPlain ||
+      b.form > kBpExact)
+    return hipErrorInvalidValue;
   int items = 0;
   for (int i = 0; i < b.n_frames; ++i) {
     const BpFrame& f = b.f[i];
     int tx, nt;
     bp_tiles(f.n_rows, f.n_cols, &tx, &nt);
     if (f.n_rows < 1 || f.n_cols < 1 || f.n_chirps < 1 || f.n_ch < 1 || f.n_bins < 2 || f.n_ch % b.chg != 0 ||
+        (b.form == kBpExact && (!f.rowv || !f.grpv)) || (b.form != kBpExact && (!f.rowq || !f.grpq)) ||
         f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.item_base != items ||
         (f.n_rows >= 8 && (f.n_rows + 15) / 16 > 0x7fffffff / 16) ||
         (int64_t)f.n_bins * 16 >= (int64_t)1 << 31 || (int64_t)f.n_chirps * f.n_ch >= (int64_t)1 << 31)

@@ -45,7 +45,9 @@ hipError_t launch_spectrum_pairs(const PairArgs& a, hipStream_t s);
 //  * the pixel in aperture-local wavelength units, P = (p - c) / lambda, as
 //    float4 (P'.x, P'.y, pp, corr) with P' = float(P), pp = float(|P|^2) and
 //    corr = (|P|^2 - pp) / |P|, the first-order path correction (in turns) for
-//    the rounding of pp that back-projection adds to every two-way path.
+//    the rounding of pp that back-projection adds to every two-way path;
+//  * exact-Doppler form: (P'.x, P'.y, 0, corr) with corr = 2 <P, P - P'> / |P|,
+//    the first-order correction for the rounding of P itself.
 struct TableArgs {
   const float2* pix;
   int64_t n_pix;
@@ -59,6 +61,7 @@ struct TableArgs {
   // split-phase form: pixc = (P'.x, P'.y, R, frac(2R)) with R = |P| and
   // fbase = a1 * 2R + f_doppler (the index of the reference path 2R)
   int split;
+  int exact;
   double a1;                      // bins per wavelength of path
   float* fbase;                   // [n_pix] (split only)
 };
@@ -82,6 +85,11 @@ struct BpFrame {
   const float4* pairs;    // [n_chirps * n_ch][n_bins]
   const float4* rowq;     // [n_chirps * n_ch]: (-2 q_rx.x, -2 q_rx.y, |q_rx|^2, 0)
   const float4* grpq;     // [n_chirps * n_ch / chg]: (-2 q_tx.x, -2 q_tx.y, |q_tx|^2, 0)
+  // exact-Doppler form (Alg. 1): per row (q_rx.x, q_rx.y, kd v.x, kd v.y) and
+  // per TX group (q_tx.x, q_tx.y, kd v.x, kd v.y); kd v in bins per unit radial
+  // speed, so <P - q, kd v> / |P - q| is the Doppler index shift of one leg
+  const float4* rowv;
+  const float4* grpv;
   float2* out;            // [n_kb][n_pix]: image (n_kb == 1) or partial images
   int n_chirps, n_ch, n_bins;
   int n_rows, n_cols;
@@ -95,12 +103,15 @@ struct BpFrame {
   float tx_lo_x, tx_lo_y, tx_hi_x, tx_hi_y;
   float rx_lo_x, rx_lo_y, rx_hi_x, rx_hi_y;
   float f_margin;
+  float f_slack;          // largest |Doppler index| a term can carry (exact form)
 };
 
 constexpr int kBpMaxFrames = 16;  // frames per launch (descriptors travel as kernel arguments)
 
+enum BpForm { kBpPlain = 0, kBpSplit = 1, kBpExact = 2 };
+
 struct BpBatch {
-  int chg, split, n_frames, n_items;
+  int chg, form, n_frames, n_items;
   BpFrame f[kBpMaxFrames];
 };
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s);

@@ -172,6 +172,10 @@ rc_status validate_desc(const rc_plan_desc* d) {
   if (d->cfar_margin_rel < 0) return fail(RC_EINVAL, "cfar_margin_rel must be >= 0");
   if (d->precision != RC_PREC_FP32 && d->precision != RC_PREC_FP32_SPLIT)
     return fail(RC_EINVAL, "unknown precision %d", (int)d->precision);
+  if (d->doppler != RC_DOPPLER_AVERAGE && d->doppler != RC_DOPPLER_EXACT)
+    return fail(RC_EINVAL, "unknown Doppler mode %d", (int)d->doppler);
+  if (d->doppler == RC_DOPPLER_EXACT && d->precision != RC_PREC_FP32)
+    return fail(RC_EINVAL, "the exact-Doppler form is single precision only");
   for (rc_window_kind k : {d->range_window, d->sar_window})
     if (k != RC_WIN_RECT && k != RC_WIN_HANN && k != RC_WIN_KAISER)
       return fail(RC_EINVAL, "unknown window kind %d", (int)k);
@@ -296,15 +300,23 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
     x = (float)((q[0] - cen_x) * inv_lam);
     y = (float)((q[1] - cen_y) * inv_lam);
   };
+  const bool exact = d.doppler == RC_DOPPLER_EXACT;
+  double vmax = 0;
   for (int64_t r = 0; r < rows; ++r) {
     float x, y;
+    // exact form: positions and kd v(m) (bins per unit radial speed)
+    const int64_t m = r / f.n_channels;
+    const float kvx = (float)(kd * f.vel[2 * m]), kvy = (float)(kd * f.vel[2 * m + 1]);
     local(f.q_rx + 2 * r, x, y);
-    rowq[r] = make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
+    rowq[r] = exact ? make_float4(x, y, kvx, kvy)
+                    : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
     rlx = std::min(rlx, x); rly = std::min(rly, y); rhx = std::max(rhx, x); rhy = std::max(rhy, y);
     local(f.q_tx + 2 * r, x, y);
     if (r % chg == 0)
-      grpq[r / chg] = make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
+      grpq[r / chg] = exact ? make_float4(x, y, kvx, kvy)
+                            : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
     tlx = std::min(tlx, x); tly = std::min(tly, y); thx = std::max(thx, x); thy = std::max(thy, y);
+    vmax = std::max(vmax, std::hypot((double)f.vel[2 * m], (double)f.vel[2 * m + 1]));
   }
   double vx = 0, vy = 0;
   for (int m = 0; m < f.n_chirps; ++m) {
@@ -365,6 +377,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   ta.fd = s.fd;
   ta.pixc = s.pixc;
   ta.split = d.precision == RC_PREC_FP32_SPLIT;
+  ta.exact = exact;
   ta.a1 = a1 * lam;
   ta.fbase = s.fbase;
   RC_HIP(rc::launch_pixel_tables(ta, st));
@@ -379,8 +392,12 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   ba.pixc = s.pixc;
   ba.fidx = d.precision == RC_PREC_FP32_SPLIT ? s.fbase : s.fd;
   ba.pairs = s.pairs;
-  ba.rowq = d_rowq;
-  ba.grpq = d_grpq;
+  ba.rowq = exact ? nullptr : d_rowq;
+  ba.grpq = exact ? nullptr : d_grpq;
+  ba.rowv = exact ? d_rowq : nullptr;
+  ba.grpv = exact ? d_grpq : nullptr;
+  // each leg's Doppler index shift is at most kd |v|
+  ba.f_slack = exact ? (float)(2.0 * kd * vmax * (1.0 + 1e-6)) : 0.f;
   ba.out = n_kb > 1 ? s.partials : img;
   ba.n_chirps = f.n_chirps;
   ba.n_ch = f.n_channels;
@@ -568,7 +585,8 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     if (done[i]) continue;
     rc::BpBatch b{};
     b.chg = chg[i];
-    b.split = p->d.precision == RC_PREC_FP32_SPLIT;
+    b.form = p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
+             : p->d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
     for (int j = i; j < n_frames && b.n_frames < rc::kBpMaxFrames; ++j) {
       if (done[j] || chg[j] != chg[i]) continue;
       rc::BpFrame fj = bpf[j];

@@ -47,7 +47,11 @@ __global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableArgs a) {
   const double pp = lx * lx + ly * ly;
   const float ppf = (float)pp;
   const double R = sqrt(pp);
-  if (a.split) {
+  if (a.exact) {
+    const float fx = (float)lx, fy = (float)ly;
+    const double corr = R > 0.0 ? 2.0 * (lx * (lx - fx) + ly * (ly - fy)) / R : 0.0;
+    a.pixc[i] = make_float4(fx, fy, 0.f, (float)corr);
+  } else if (a.split) {
     const double two_r = 2.0 * R;
     a.pixc[i] = make_float4((float)lx, (float)ly, (float)R, (float)(two_r - floor(two_r)));
     a.fbase[i] = (float)(a.a1 * two_r + a.kd * r);

@@ -27,6 +27,8 @@ RC_WIN_RECT, RC_WIN_HANN, RC_WIN_KAISER = 0, 1, 2
 WINDOWS = {"rect": RC_WIN_RECT, "hann": RC_WIN_HANN, "kaiser": RC_WIN_KAISER}
 # rc_precision
 RC_PREC_FP32, RC_PREC_FP32_SPLIT = 0, 1
+# rc_doppler_mode
+RC_DOPPLER_AVERAGE, RC_DOPPLER_EXACT = 0, 1
 # rc_input_kind
 RC_INPUT_RAW, RC_INPUT_SPECTRUM = 0, 1
 RC_DET_NEAR_THRESHOLD = 1
@@ -54,6 +56,7 @@ class rc_plan_desc(C.Structure):
         ("sar_window", C.c_int),
         ("sar_kaiser_beta", C.c_double),
         ("precision", C.c_int),
+        ("doppler", C.c_int),
         ("cfar_guard", C.c_int32),
         ("cfar_train", C.c_int32),
         ("cfar_pfa", C.c_double),
@@ -200,6 +203,7 @@ class PlanConfig:
     sar_window: str = "hann"
     sar_kaiser_beta: float = 4.0
     precision: int = RC_PREC_FP32
+    doppler: int = RC_DOPPLER_AVERAGE
     cfar_guard: int = 2
     cfar_train: int = 8
     cfar_pfa: float = 1e-4
@@ -214,7 +218,7 @@ class PlanConfig:
             self.n_samples_max, self.n_fft_max, self.n_bins_max, self.n_chirps_max,
             self.n_channels_max, self.n_pix_max, self.max_frames_in_flight, self.max_detections,
             WINDOWS[self.range_window], self.range_kaiser_beta, WINDOWS[self.sar_window],
-            self.sar_kaiser_beta, self.precision, self.cfar_guard, self.cfar_train, self.cfar_pfa,
+            self.sar_kaiser_beta, self.precision, self.doppler, self.cfar_guard, self.cfar_train, self.cfar_pfa,
             self.cfar_margin_rel, self.hbm_budget_bytes, int(self.stage_timing))
 
 

@@ -79,8 +79,9 @@ def oracle_constants(frame):
 
 
 def run_oracle(frame, spectrum=None, pix_index=None, sar_window="hann", range_window="hann",
-               cfar=(2, 8, 1e-4)):
-    """FP64 pipeline; with pix_index only those pixels are formed (no CFAR)."""
+               cfar=(2, 8, 1e-4), doppler="average"):
+    """FP64 pipeline; with pix_index only those pixels are formed (no CFAR).
+    doppler="exact" forms the image with Alg. 1 instead of Alg. 2."""
     k = oracle_constants(frame)
     if spectrum is None:
         s = O.range_compress(frame.raw, O.window(range_window, frame.cfg.n_samples), frame.n_fft,
@@ -92,7 +93,10 @@ def run_oracle(frame, spectrum=None, pix_index=None, sar_window="hann", range_wi
         pix = pix[pix_index]
     fd = O.doppler_table(pix, frame.q_tx, frame.q_rx, frame.vel, k["kd"])
     w = O.window(sar_window, frame.cfg.n_chirps)
-    P = O.bp_alg2(pix, frame.q_tx, frame.q_rx, fd, s, w, k["a1"], k["a2"])
+    if doppler == "exact":
+        P = O.bp_alg1(pix, frame.q_tx, frame.q_rx, frame.vel, s, w, R["f0"], k["mu"], k["df"])
+    else:
+        P = O.bp_alg2(pix, frame.q_tx, frame.q_rx, fd, s, w, k["a1"], k["a2"])
     out = {"spectrum": s, "doppler": fd, "image": P, "w_sar": w, "k": k}
     if pix_index is None and cfar is not None:
         pw = (np.abs(P) ** 2).reshape(frame.n_rows, frame.n_cols)

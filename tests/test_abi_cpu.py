@@ -52,7 +52,7 @@ int main(void) {
   printf("rc_radar %zu\nrc_plan_desc %zu\nrc_frame %zu\nrc_detection %zu\n",
          sizeof(rc_radar), sizeof(rc_plan_desc), sizeof(rc_frame), sizeof(rc_detection));
   P(rc_plan_desc, radar) P(rc_plan_desc, n_pix_max) P(rc_plan_desc, range_window)
-  P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision)
+  P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision) P(rc_plan_desc, doppler)
   P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
   P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
   P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out)
@@ -93,7 +93,8 @@ def test_descriptor_validation(rc):
     assert good >= 128 * 4 * 256 * 16 + 65536 * (8 + 4 + 8 + 16)
     bad = [dict(n_fft_max=500), dict(n_fft_max=8192, n_samples_max=256), dict(n_bins_max=1024),
            dict(n_samples_max=1024), dict(cfar_guard=10, cfar_train=10), dict(cfar_pfa=1.5),
-           dict(max_frames_in_flight=0), dict(precision=7), dict(range_window="bogus")]
+           dict(max_frames_in_flight=0), dict(precision=7), dict(range_window="bogus"), dict(doppler=5),
+           dict(doppler=1, precision=1)]
     for kw in bad:
         with pytest.raises((rc.RcError, KeyError)) as ei:
             rc.slot_bytes(_cfg(rc, **kw))

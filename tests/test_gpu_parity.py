@@ -158,6 +158,36 @@ def test_bp_parity_indices_out_of_range(rc, torch, precision):
     _check_image("bp_out_of_range", fr, out["image"], ora, precision)
 
 
+@pytest.mark.parametrize("n_tx,n_rx,yaw", [(1, 4, 0.0), (4, 4, 25.0), (1, 8, -40.0)])
+def test_alg1_exact_doppler_parity(rc, torch, n_tx, n_rx, yaw):
+    """Alg. 1 (per-chirp radial velocities) on straight and curved drives; on a
+    curved drive it must differ from Alg. 2 by more than its tolerance."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="alg1", n_samples=64, n_chirps=24,
+                              n_tx=n_tx, n_rx=n_rx, nx=45, ny=37, box=(-4.0, 4.0, 1.5, 7.0), speed=8.0,
+                              yaw_rate=yaw, n_targets=1, noise=False, seed=17 + n_rx)
+    fr = synth.make_frame(cfg)
+    rng = np.random.default_rng(200 + n_rx)
+    spec = synth.random_spectrum(rng, (cfg.n_chirps, cfg.n_channels, fr.n_bins))
+    with rc.Plan(SC.plan_config(rc, [fr], doppler=rc.RC_DOPPLER_EXACT)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, spectrum=spec)
+    ora = SC.run_oracle(fr, spectrum=spec, cfar=None, doppler="exact")
+    _check_image(f"alg1_tx{n_tx}_rx{n_rx}_yaw{yaw}", fr, out["image"], ora, PLAIN)
+    if yaw != 0.0:
+        # the per-chirp Doppler of a turning vehicle is visible: Alg. 2 (averaged)
+        # departs from Alg. 1 by far more than the GPU's error against Alg. 1
+        alg2 = SC.run_oracle(fr, spectrum=spec, cfar=None)["image"]
+        gpu_err = np.abs(out["image"].astype(np.complex128) - ora["image"]).max()
+        assert np.abs(alg2 - ora["image"]).max() > 5 * gpu_err
+
+
+def test_end_to_end_exact_doppler(rc, torch):
+    fr = SC.small_frame(nx=96, ny=80, n_chirps=64)
+    with rc.Plan(SC.plan_config(rc, [fr], doppler=rc.RC_DOPPLER_EXACT)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch)
+    ora = SC.run_oracle(fr, cfar=None, doppler="exact")
+    _check_image("end_to_end_exact", fr, out["image"], ora, PLAIN)
+
+
 @pytest.mark.parametrize("n_rows,n_cols", [(1, 300), (5, 70), (8, 8), (9, 17)])
 def test_bp_parity_small_lattices(rc, torch, n_rows, n_cols):
     cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="lat", n_samples=32, n_chirps=6, n_rx=4,
