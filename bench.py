@@ -98,7 +98,8 @@ def cpu_baseline(frame, budget_s: float = 20.0):
     }
 
 
-def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup):
+def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup,
+                  doppler=0, want_image=False):
     """Times `steps` frames through rc_process_batch + rc_detections on one stream."""
     dev = torch.device("cuda:0")
     cfg = frame.cfg
@@ -109,7 +110,7 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
                        n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
                        n_pix_max=n_pix, max_frames_in_flight=2, max_detections=1 << 16,
-                       precision=precision, stage_timing=True)
+                       precision=precision, doppler=doppler, stage_timing=True)
     stream = torch.cuda.current_stream()
     lat, stages, n_det = [], [], 0
     with rc.Plan(pc) as plan:
@@ -135,7 +136,10 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
             n_det = len(dets)
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
-    return {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
+    res = {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
+    if want_image:
+        res["image"] = img.cpu().numpy().view(np.complex64).reshape(-1)
+    return res
 
 
 def paper_config(rc, synth, torch, steps):
@@ -165,6 +169,60 @@ def paper_config(rc, synth, torch, steps):
         "paper_tab2_row8": {"gpu": "GTX 1080 Ti (FP32, pyCUDA)", "bp_ms": 15.5, "total_ms": 18.8,
                             "bp_terms": 165061 * 1024 * 8, "bp_terms_per_s": 165061 * 1024 * 8 / 15.5e-3},
     }
+
+
+def _target_gain_db(img, pix, targets, ref_img, ref_pix, rad=0.06):
+    """Mean over point targets of 20 log10(peak |P| near the target / the same
+    in the reference image): the synthetic stand-in for the paper's region SNR."""
+    out = []
+    for t in targets:
+        a = np.abs(img[np.hypot(pix[:, 0] - t[0], pix[:, 1] - t[1]) < rad])
+        b = np.abs(ref_img[np.hypot(ref_pix[:, 0] - t[0], ref_pix[:, 1] - t[1]) < rad])
+        if a.size and b.size and b.max() > 0:
+            out.append(20 * np.log10(a.max() / b.max()))
+    return float(np.mean(out)) if out else None
+
+
+def ablation(rc, synth, torch, steps=3):
+    """The measures of the paper's Tab. II on one synthetic frame of its
+    reference setting (1024 chirps x 16 RX, 30 m x 30 m): Alg. 1 on the 2.5 cm
+    Cartesian grid (reference), then the Doppler table (Alg. 2), the polar grid
+    (Sec. III-E), 8 of the 16 RX (Sec. III-F) and all combined.  Reports BP
+    time and its share of the reference, next to the paper's shares, and the
+    mean coherent gain change at the point targets."""
+    cfg = synth.CONFIGS["paper-ref"]
+    frame = synth.make_frame(cfg, device="cuda")
+    q = np.concatenate([frame.q_tx.reshape(-1, 2), frame.q_rx.reshape(-1, 2)])
+    g = rc.grid_polar_params(synth.RADAR, cfg.box, (float(q[:, 0].mean()), float(q[:, 1].mean())),
+                             float(np.ptp(q[:, 0])))
+    polar = rc.grid_polar(g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"])
+    half = synth.Frame(**{**frame.__dict__, "raw": np.ascontiguousarray(frame.raw[:, :8]),
+                          "q_tx": np.ascontiguousarray(frame.q_tx[:, :8]),
+                          "q_rx": np.ascontiguousarray(frame.q_rx[:, :8]),
+                          "cfg": synth.dataclasses.replace(cfg, n_rx=8)})
+    runs = {
+        "ref_alg1_cartesian_16rx": (frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_EXACT),
+        "doppler_table": (frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_AVERAGE),
+        "polar_grid": (frame, polar, g["nth"], g["nr"], rc.RC_DOPPLER_AVERAGE),
+        "rx_8": (half, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_AVERAGE),
+        "combined": (half, polar, g["nth"], g["nr"], rc.RC_DOPPLER_AVERAGE),
+    }
+    paper = {"doppler_table": (63.7, 65.0), "polar_grid": (11.9, 10.4), "rx_8": (51.7, 52.6),
+             "combined": (2.9, 2.4)}
+    out, ref_ms, ref_img = {}, None, None
+    for name, (fr, pix, nr, nc, dop) in runs.items():
+        run = time_pipeline(rc, synth, torch, fr, pix, nr, nc, rc.RC_PREC_FP32, steps, 1, doppler=dop,
+                            want_image=True)
+        bp_ms = float(run["stages"][:, 2].mean())
+        ref_ms = ref_ms or bp_ms
+        if ref_img is None:
+            ref_img = run["image"]
+        out[name] = {"bp_ms": bp_ms, "bp_share_pct": 100.0 * bp_ms / ref_ms,
+                     "paper_share_pct_gpu1_gpu2": paper.get(name),
+                     "target_gain_db_vs_ref": _target_gain_db(run["image"], pix, frame.targets, ref_img,
+                                                               frame.pix),
+                     "pixels": nr * nc}
+    return out
 
 
 def make_sensors(rc, synth, torch, n_sensors, seed=3000):
@@ -347,6 +405,7 @@ def main(argv=None):
             "frames_per_s": sp["fps"], "backprojection_ms": float(sp["stages"][:, 2].mean()),
             "p99_ms": 1e3 * float(np.percentile(sp["lat"], 99))}
         out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
+        out["tab2_ablation"] = ablation(rc, synth, torch)
         sensors = make_sensors(rc, synth, torch, 32)
         out["batched_mixed"] = batched_mixed(rc, synth, torch, sensors)
         if args.serve_seconds > 0:

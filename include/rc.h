@@ -109,8 +109,12 @@ typedef struct rc_plan_desc {
   int32_t cfar_guard;           /* guard cells each side (2)                      */
   int32_t cfar_train;           /* training cells each side beyond guard (8)      */
   double cfar_pfa;              /* design false-alarm probability (1e-4)          */
-  double cfar_margin_rel;       /* cells with |power - thr| <= margin * thr are
-                                   flagged RC_DET_NEAR_THRESHOLD                   */
+  double cfar_margin_rel;       /* near-threshold band: |power - thr| <= margin * thr */
+  int32_t max_rechecks;         /* near-threshold cells per frame whose decision is
+                                   re-evaluated in double precision (their pixel and
+                                   training pixels formed again by back-projection in
+                                   double); 0 disables the recheck.  Cells of the band
+                                   not rechecked are flagged RC_DET_NEAR_THRESHOLD.  */
   int64_t hbm_budget_bytes;     /* 0 = unlimited                                  */
   int32_t stage_timing;         /* nonzero: bracket every stage with timing events
                                    (read with rc_stage_times)                      */
@@ -143,7 +147,8 @@ typedef struct rc_frame {
                                    beat spectrum before w_sar, or NULL            */
 } rc_frame;
 
-#define RC_DET_NEAR_THRESHOLD 1u
+#define RC_DET_NEAR_THRESHOLD 1u  /* in the band, decided in single precision */
+#define RC_DET_RECHECKED 2u       /* in the band, decided by the double-precision recheck */
 
 typedef struct rc_detection {
   int32_t pixel;                /* flat lattice index row * n_cols + col          */

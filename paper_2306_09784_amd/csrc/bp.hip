@@ -31,9 +31,11 @@
 //
 // Work distribution: one launch covers a batch of frames; its work items are
 // (frame, chirp block, 16 x 16 tile).  Workgroups are dispatched to the eight
-// XCDs round robin, so workgroup w is given item (w % 8) * ceil(n / 8) + w / 8:
-// each XCD walks a contiguous range of items, i.e. neighbouring tiles of one
-// chirp block, whose gathers hit the same table rows in that XCD's L2.
+// XCDs round robin, so workgroup w runs on XCD k = w % 8 as its slot w / 8.
+// The slots of an XCD walk the frames in order (the caller sorts them by
+// cost, largest first) and, within a frame, the k-th contiguous eighth of its
+// items: neighbouring tiles of one chirp block, whose gathers hit the same
+// table rows in that XCD's L2, while every frame is spread over all XCDs.
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -43,165 +45,122 @@ constexpr int kThreads = 256;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 
-// Split-phase form: d = |P - q| = R + delta with delta = N / (d + R) and
-// N = |P - q|^2 - R^2 = |q|^2 - 2 P.q (two FMAs), d = sqrt(R^2 + N).  Only
-// delta (|delta| <= |q|) and the reference phase frac(2R) enter the phase, so
-// its rounding error scales with the aperture size, not with the range.
-template <int CHG, bool CHECKED>
-__device__ __forceinline__ void bp_terms_split(const BpFrame& a, int row_begin, int row_end, const float4 p,
-                                               const float fb, float& out_re, float& out_im) {
-  const float nbm1 = (float)(a.n_bins - 1);
-  const int row_bytes = a.n_bins * 16;
-  const size_t gstride = (size_t)CHG * a.n_bins;
-  const float4* rq = a.rowq + row_begin;
-  const float4* gq = a.grpq + row_begin / CHG;
-  const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
-  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  for (int row0 = row_begin; row0 < row_end; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
-    const float4 t = gq[0];
-    const float nt = fmaf(t.x, p.x, fmaf(t.y, p.y, t.z));
-    const float dlt_tx = nt * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, nt)) + p.z);
-#pragma unroll
-    for (int j = 0; j < CHG; ++j) {
-      const float4 q = rq[j];
-      const float nr = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
-      const float dlt = dlt_tx + nr * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, nr)) + p.z);
-      const float f = fmaf(a.a1, dlt, fb);
-      int i;
-      float phi;
-      if (CHECKED) {
-        const float fl = floorf(f);
-        phi = f - fl;
-        i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;
-      } else {
-        i = (int)f;
-        phi = __builtin_amdgcn_fractf(f);
-      }
-      const float turn = __builtin_amdgcn_fractf(p.w + dlt);
-      const float sn = __builtin_amdgcn_sinf(turn);
-      const float cs = __builtin_amdgcn_cosf(turn);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(tab + (size_t)j * a.n_bins), (short)0, row_bytes, kRsrcWord3);
-      const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
-      const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
-      const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
-      if (j & 1) {
-        re1 = fmaf(cs, vr, re1);
-        re1 = fmaf(sn, vi, re1);
-        im1 = fmaf(cs, vi, im1);
-        im1 = fmaf(-sn, vr, im1);
-      } else {
-        re0 = fmaf(cs, vr, re0);
-        re0 = fmaf(sn, vi, re0);
-        im0 = fmaf(cs, vi, im0);
-        im0 = fmaf(-sn, vr, im0);
-      }
-    }
+// Per-form geometry of one term.  Plain (Alg. 2): d = sqrt(|P|^2 + |q|^2 -
+// 2 P.q) from the per-row uniforms (-2 q, |q|^2) and the pixel's |P|^2 split
+// into a float and a correction.  Split-phase: d = R + delta with
+// delta = N / (d + R), N = |P - q|^2 - R^2 = |q|^2 - 2 P.q (two FMAs),
+// d = sqrt(R^2 + N); only delta (|delta| <= |q|) and the reference phase
+// frac(2R) enter the phase, so its rounding error scales with the aperture
+// size, not with the range.  Exact (Alg. 1): each leg also contributes its own
+// Doppler index shift <P - q, kd v(m)> / |P - q| from the chirp's velocity.
+template <int FORM>
+struct Leg {
+  float d;    // plain: distance (TX leg: + correction); split: delta; exact: distance
+  float dop;  // exact only: Doppler index shift of the leg
+};
+
+template <int FORM>
+__device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p) {
+  Leg<FORM> l;
+  if constexpr (FORM == kBpExact) {
+    const float x = p.x - q.x, y = p.y - q.y;
+    l.d = __builtin_amdgcn_sqrtf(fmaf(x, x, y * y));
+    l.dop = fmaf(x, q.z, y * q.w) * __builtin_amdgcn_rcpf(l.d);
+  } else if constexpr (FORM == kBpSplit) {
+    const float n = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
+    l.d = n * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, n)) + p.z);
+    l.dop = 0.f;
+  } else {
+    l.d = __builtin_amdgcn_sqrtf(fmaf(q.x, p.x, fmaf(q.y, p.y, p.z)) + q.z);
+    l.dop = 0.f;
   }
-  out_re = re0 + re1;
-  out_im = im0 + im1;
+  return l;
 }
 
-// Exact-Doppler form (Alg. 1): each leg also contributes its own Doppler
-// index shift <P - q, kd v(m)> / |P - q| from the chirp's velocity, so the
-// distances need the difference vector and a reciprocal.
-template <int CHG, bool CHECKED>
-__device__ __forceinline__ void bp_terms_exact(const BpFrame& a, int row_begin, int row_end, const float4 p,
-                                               float& out_re, float& out_im) {
-  const float nbm1 = (float)(a.n_bins - 1);
-  const int row_bytes = a.n_bins * 16;
-  const size_t gstride = (size_t)CHG * a.n_bins;
-  const float4* rv = a.rowv + row_begin;
-  const float4* gv = a.grpv + row_begin / CHG;
-  const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
-  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  for (int row0 = row_begin; row0 < row_end; row0 += CHG, rv += CHG, ++gv, tab += gstride) {
-    const float4 t = gv[0];
-    const float tx = p.x - t.x, ty = p.y - t.y;
-    const float d_tx = __builtin_amdgcn_sqrtf(fmaf(tx, tx, ty * ty));
-    const float dop_tx = fmaf(tx, t.z, ty * t.w) * __builtin_amdgcn_rcpf(d_tx);
-    const float d_tx_c = d_tx + p.w;
-#pragma unroll
-    for (int j = 0; j < CHG; ++j) {
-      const float4 q = rv[j];
-      const float rx = p.x - q.x, ry = p.y - q.y;
-      const float d_rx = __builtin_amdgcn_sqrtf(fmaf(rx, rx, ry * ry));
-      const float dop = dop_tx + fmaf(rx, q.z, ry * q.w) * __builtin_amdgcn_rcpf(d_rx);
-      const float d_hyp = d_tx_c + d_rx;
-      const float f = fmaf(a.a1, d_hyp, dop);
-      int i;
-      float phi;
-      if (CHECKED) {
-        const float fl = floorf(f);
-        phi = f - fl;
-        i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;
-      } else {
-        i = (int)f;
-        phi = __builtin_amdgcn_fractf(f);
-      }
-      const float turn = __builtin_amdgcn_fractf(d_hyp);
-      const float sn = __builtin_amdgcn_sinf(turn);
-      const float cs = __builtin_amdgcn_cosf(turn);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(tab + (size_t)j * a.n_bins), (short)0, row_bytes, kRsrcWord3);
-      const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
-      const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
-      const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
-      if (j & 1) {
-        re1 = fmaf(cs, vr, re1);
-        re1 = fmaf(sn, vi, re1);
-        im1 = fmaf(cs, vi, im1);
-        im1 = fmaf(-sn, vr, im1);
-      } else {
-        re0 = fmaf(cs, vr, re0);
-        re0 = fmaf(sn, vi, re0);
-        im0 = fmaf(cs, vi, im0);
-        im0 = fmaf(-sn, vr, im0);
-      }
-    }
-  }
-  out_re = re0 + re1;
-  out_im = im0 + im1;
-}
+// One pipeline stage: U terms whose table loads are in flight.
+template <int U>
+struct Stage {
+  u32x4 e[U];
+  float phi[U];
+  float turn[U];
+};
 
-template <int CHG, bool CHECKED>
+// The terms of rows [row_begin, row_end) for one pixel, software-pipelined:
+// the table loads of the next U rows are issued before the phases and
+// multiply-accumulates of the current U rows, so their latency overlaps the
+// transcendentals.  U = min(CHG, 4) rows per stage; the TX leg is evaluated
+// once per group of CHG rows.
+template <int CHG, int FORM, bool CHECKED>
 __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int row_end, const float4 p,
-                                         const float fdp, float& out_re, float& out_im) {
+                                         const float fidx, float& out_re, float& out_im) {
+  constexpr bool EXACT = FORM == kBpExact;
+  constexpr int U = CHG < 4 ? CHG : 4;
+  constexpr int UPG = CHG / U;  // stages per TX group
   const float nbm1 = (float)(a.n_bins - 1);
   const int row_bytes = a.n_bins * 16;
-  const size_t gstride = (size_t)CHG * a.n_bins;
-  const float4* rq = a.rowq + row_begin;
-  const float4* gq = a.grpq + row_begin / CHG;
+  const float4* rq = (EXACT ? a.rowv : a.rowq) + row_begin;
+  const float4* gq = (EXACT ? a.grpv : a.grpq) + row_begin / CHG;
   const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
+  const int n = row_end - row_begin;  // a multiple of CHG
+  // per-pixel index base: plain f_doppler; split the index of the reference path
+  const float fb = fidx;
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  for (int row0 = row_begin; row0 < row_end; row0 += CHG, rq += CHG, ++gq, tab += gstride) {
-    const float4 t = gq[0];
-    const float d_tx = __builtin_amdgcn_sqrtf(fmaf(t.x, p.x, fmaf(t.y, p.y, p.z)) + t.z) + p.w;
+  Leg<FORM> tx;
+
+  auto tx_leg = [&](int r) {
+    tx = leg<FORM>(gq[r / CHG], p);
+    if constexpr (FORM == kBpPlain) tx.d += p.w;
+    if constexpr (FORM == kBpExact) tx.d += p.w;
+  };
+  auto issue = [&](int r, Stage<U>& st) {
+    // the stage's row uniforms as one vector, so they arrive in one scalar load
+    typedef float uvec __attribute__((ext_vector_type(4 * U)));
+    const uvec u = *reinterpret_cast<const uvec*>(rq + r);
+    float4 q[U];
 #pragma unroll
-    for (int j = 0; j < CHG; ++j) {
-      const float4 q = rq[j];
-      const float d_hyp = d_tx + __builtin_amdgcn_sqrtf(fmaf(q.x, p.x, fmaf(q.y, p.y, p.z)) + q.z);
-      const float f = fmaf(a.a1, d_hyp, fdp);
+    for (int j = 0; j < U; ++j) q[j] = make_float4(u[4 * j], u[4 * j + 1], u[4 * j + 2], u[4 * j + 3]);
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const Leg<FORM> rx = leg<FORM>(q[j], p);
+      float f, turn;
+      if constexpr (FORM == kBpSplit) {
+        const float dlt = tx.d + rx.d;
+        f = fmaf(a.a1, dlt, fb);
+        turn = __builtin_amdgcn_fractf(p.w + dlt);
+      } else if constexpr (FORM == kBpExact) {
+        const float d_hyp = tx.d + rx.d;
+        f = fmaf(a.a1, d_hyp, tx.dop + rx.dop);
+        turn = __builtin_amdgcn_fractf(d_hyp);
+      } else {
+        const float d_hyp = tx.d + rx.d;
+        f = fmaf(a.a1, d_hyp, fb);
+        turn = __builtin_amdgcn_fractf(d_hyp);
+      }
       int i;
-      float phi;
       if (CHECKED) {
         const float fl = floorf(f);
-        phi = f - fl;
+        st.phi[j] = f - fl;
         i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;  // -1: outside the descriptor -> zeros
       } else {
         i = (int)f;                                  // f >= 0 here: truncation is floor
-        phi = __builtin_amdgcn_fractf(f);
+        st.phi[j] = __builtin_amdgcn_fractf(f);
       }
-      const float turn = __builtin_amdgcn_fractf(d_hyp);
-      const float sn = __builtin_amdgcn_sinf(turn);  // sin(2 pi turn)
-      const float cs = __builtin_amdgcn_cosf(turn);
+      st.turn[j] = turn;
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(tab + (size_t)j * a.n_bins), (short)0, row_bytes, kRsrcWord3);
-      const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
-      const float vr = fmaf(phi, __uint_as_float(e.z), __uint_as_float(e.x));
-      const float vi = fmaf(phi, __uint_as_float(e.w), __uint_as_float(e.y));
+          (void*)(tab + (size_t)(r + j) * a.n_bins), (short)0, row_bytes, kRsrcWord3);
+      st.e[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
+    }
+  };
+  // PAR selects the accumulator pair of a single-row stage
+  auto consume = [&](const Stage<U>& st, int par) {
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const float sn = __builtin_amdgcn_sinf(st.turn[j]);  // sin(2 pi turn)
+      const float cs = __builtin_amdgcn_cosf(st.turn[j]);
+      const float vr = fmaf(st.phi[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
+      const float vi = fmaf(st.phi[j], __uint_as_float(st.e[j].w), __uint_as_float(st.e[j].y));
       // (cs - i sn) (vr + i vi)
-      if (j & 1) {
+      if (((U == 1) ? par : j) & 1) {
         re1 = fmaf(cs, vr, re1);
         re1 = fmaf(sn, vi, re1);
         im1 = fmaf(cs, vi, im1);
@@ -213,6 +172,27 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
         im0 = fmaf(-sn, vr, im0);
       }
     }
+  };
+  auto step = [&](int r, Stage<U>& st) {
+    if (UPG == 1 || ((r / U) & (UPG - 1)) == 0) tx_leg(r);
+    issue(r, st);
+  };
+
+  Stage<U> sa, sb;
+  step(0, sa);
+  int r = U;
+  for (; r + U < n; r += 2 * U) {
+    step(r, sb);
+    consume(sa, 0);
+    step(r + U, sa);
+    consume(sb, 1);
+  }
+  if (r < n) {
+    step(r, sb);
+    consume(sa, 0);
+    consume(sb, 1);
+  } else {
+    consume(sa, 0);
   }
   out_re = re0 + re1;
   out_im = im0 + im1;
@@ -234,19 +214,19 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   constexpr bool SPLIT = FORM == kBpSplit;
   constexpr bool EXACT = FORM == kBpExact;
   const int w = blockIdx.x;
-  const int per = (b.n_items + 7) >> 3;
+  const int xcd = w & 7;
   const int slot = w >> 3;
-  const int item = (w & 7) * per + slot;
-  if (slot >= per || item >= b.n_items) return;
+  if (slot >= b.n_slots) return;
   int fi = 0;
-  while (fi + 1 < b.n_frames && item >= b.f[fi + 1].item_base) ++fi;
+  while (fi + 1 < b.n_frames && slot >= b.f[fi + 1].slot_base) ++fi;
   // a by-value copy read before any lane-dependent branch keeps every
   // descriptor field in scalar registers
   const BpFrame a = b.f[__builtin_amdgcn_readfirstlane(fi)];
   // the integer divisions below run on the VALU; readfirstlane hands their
   // (workgroup-uniform) results back to scalar registers so that the table
   // descriptors derived from them stay scalar
-  const int local = item - a.item_base;
+  const int local = xcd * a.chunk + (slot - a.slot_base);
+  if (local >= a.n_kb * a.n_tiles) return;
   const int kb = __builtin_amdgcn_readfirstlane(local / a.n_tiles);
   const int tile = local - kb * a.n_tiles;
   const int ty = __builtin_amdgcn_readfirstlane(tile / a.tiles_x);
@@ -288,22 +268,11 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   const int row_begin = m0 * a.n_ch, row_end = m1 * a.n_ch;
 
   float re, im;
-  if (EXACT) {
-    if (__all(inside))
-      bp_terms_exact<CHG, false>(a, row_begin, row_end, p, re, im);
-    else
-      bp_terms_exact<CHG, true>(a, row_begin, row_end, p, re, im);
-  } else if (SPLIT) {
-    if (__all(inside))
-      bp_terms_split<CHG, false>(a, row_begin, row_end, p, fi_p, re, im);
-    else
-      bp_terms_split<CHG, true>(a, row_begin, row_end, p, fi_p, re, im);
-  } else {
-    if (__all(inside))
-      bp_terms<CHG, false>(a, row_begin, row_end, p, fdp, re, im);
-    else
-      bp_terms<CHG, true>(a, row_begin, row_end, p, fdp, re, im);
-  }
+  const float fb = SPLIT ? fi_p : fdp;
+  if (__all(inside))
+    bp_terms<CHG, FORM, false>(a, row_begin, row_end, p, fb, re, im);
+  else
+    bp_terms<CHG, FORM, true>(a, row_begin, row_end, p, fb, re, im);
   if (live) a.out[(int64_t)kb * a.n_rows * a.n_cols + idx] = make_float2(re, im);
 }
 
@@ -357,24 +326,25 @@ int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps) {
 }
 
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
-  if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_items < 1 || b.chg < 1 || b.form < kBpPlain ||
+  if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_slots < 1 || b.chg < 1 || b.form < kBpPlain ||
       b.form > kBpExact)
     return hipErrorInvalidValue;
-  int items = 0;
+  int slots = 0;
   for (int i = 0; i < b.n_frames; ++i) {
     const BpFrame& f = b.f[i];
     int tx, nt;
     bp_tiles(f.n_rows, f.n_cols, &tx, &nt);
     if (f.n_rows < 1 || f.n_cols < 1 || f.n_chirps < 1 || f.n_ch < 1 || f.n_bins < 2 || f.n_ch % b.chg != 0 ||
         (b.form == kBpExact && (!f.rowv || !f.grpv)) || (b.form != kBpExact && (!f.rowq || !f.grpq)) ||
-        f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.item_base != items ||
+        f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.slot_base != slots ||
+        f.chunk != (f.n_kb * nt + 7) / 8 ||
         (f.n_rows >= 8 && (f.n_rows + 15) / 16 > 0x7fffffff / 16) ||
         (int64_t)f.n_bins * 16 >= (int64_t)1 << 31 || (int64_t)f.n_chirps * f.n_ch >= (int64_t)1 << 31)
       return hipErrorInvalidValue;
-    items += f.n_kb * nt;
+    slots += f.chunk;
   }
-  if (items != b.n_items) return hipErrorInvalidValue;
-  const int64_t blocks = (int64_t)((b.n_items + 7) / 8) * 8;
+  if (slots != b.n_slots) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t)b.n_slots * 8;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
   switch (b.chg) {

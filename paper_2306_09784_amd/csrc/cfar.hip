@@ -67,13 +67,22 @@ __global__ __launch_bounds__(kThreads) void cfar_kernel(CfarArgs a) {
   const unsigned long long word = __ballot(det);
   if (r < a.n_rows && lane == 0 && blockIdx.x < (unsigned)a.words_per_row)
     a.mask[(int64_t)r * a.words_per_row + blockIdx.x] = word;
+  const bool near = tested && fabs(p - thr) <= a.margin_rel * thr;
+  bool listed = false;
+  if (near && a.recheck_cap > 0) {
+    const int pos = atomicAdd(a.n_listed, 1);
+    if (pos < a.recheck_cap) {
+      a.listed[pos] = r * a.n_cols + c;
+      listed = true;
+    }
+  }
   if (det) {
     const int64_t cell = (int64_t)r * a.n_cols + c;
     rc_detection d;
     d.pixel = (int32_t)cell;
     d.power = (float)p;
     d.threshold = (float)thr;
-    d.flags = (fabs(p - thr) <= a.margin_rel * thr) ? RC_DET_NEAR_THRESHOLD : 0u;
+    d.flags = (near && !listed) ? RC_DET_NEAR_THRESHOLD : 0u;
     a.det_cell[cell] = d;
   }
 }

@@ -4,13 +4,20 @@
 // s[row][k] = sum_{t < n_s} w_range[t] raw[row][t] exp(-2 pi i k t / n_fft),
 // k < n_bins, computed as an n_fft-point FFT of the zero-padded row.
 //
-// Design (HBM-bound stage): each row is read once with coalesced loads,
-// windowed on the fly and scattered in bit-reversed order into LDS; the
-// decimation-in-time butterflies run in LDS two radix-2 stages at a time
-// (four elements per thread, one barrier per pair of stages); only the n_bins
-// kept bins are written, directly in the interleaved (value, slope) layout
-// that back-projection gathers with one 16-byte load per term, with the chirp
-// window w_sar[m] folded in.  Rows shorter than a wave share a workgroup.
+// Design (HBM-bound stage): a self-sorting (Stockham) FFT whose passes are
+// radix-16 butterflies held in registers, 16 samples per lane, so a 2048-point
+// row takes three passes and two exchanges through LDS instead of eleven
+// radix-2 stages.  The first pass reads the windowed samples straight from
+// HBM (coalesced: lane j of a row reads samples j + r n/16) and treats the
+// zero padding as zeros without loading it; the last pass keeps only the
+// n_bins bins that are written, directly in the interleaved (value, slope)
+// layout that back-projection gathers with one 16-byte load per term, with
+// the chirp window w_sar[m] folded in.  Pass p of radix R at stride Ns
+// multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (loaded from a
+// full-circle twiddle table the host evaluates in double) and writes output r
+// to (b / Ns) Ns R + (b mod Ns) + r Ns.  LDS rows are padded by one element
+// per 16, which keeps the stride-16 writes of the first passes free of bank
+// conflicts.  Rows shorter than 16 x 64 samples share a workgroup.
 #include "rc_kernels.hpp"
 
 namespace rc {
@@ -23,66 +30,164 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-// multiply by -i
-__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
-__global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeArgs a, int tpr) {
-  extern __shared__ float2 lds[];
-  const int n = a.n_fft;
-  const int rows_per_wg = kThreads / tpr;
-  const int lrow = threadIdx.x / tpr;
-  const int t = threadIdx.x - lrow * tpr;
-  const int64_t row = (int64_t)blockIdx.x * rows_per_wg + lrow;
+// x * exp(-2 pi i q / 16), q in [0, 8)
+template <int Q>
+__device__ __forceinline__ float2 rot16(float2 x) {
+  constexpr float c1 = 0.92387953251128674f;  // cos(pi / 8)
+  constexpr float s1 = 0.38268343236508978f;  // sin(pi / 8)
+  constexpr float h = 0.70710678118654752f;   // sqrt(1/2)
+  if constexpr (Q == 0) return x;
+  else if constexpr (Q == 4) return make_float2(x.y, -x.x);
+  else if constexpr (Q == 2) return make_float2(h * (x.x + x.y), h * (x.y - x.x));
+  else if constexpr (Q == 6) return make_float2(h * (x.y - x.x), -h * (x.x + x.y));
+  else {
+    constexpr float c = Q == 1 ? c1 : Q == 3 ? s1 : Q == 5 ? -s1 : -c1;
+    constexpr float s = Q == 1 ? s1 : Q == 3 ? c1 : Q == 5 ? c1 : s1;
+    return make_float2(fmaf(x.x, c, x.y * s), fmaf(x.y, c, -x.x * s));
+  }
+}
+
+template <int R>
+constexpr int bitrev(int r) {
+  int o = 0;
+  for (int b = 1; b < R; b <<= 1) o = (o << 1) | ((r & b) ? 1 : 0);
+  return o;
+}
+
+// In-register DFT of R = 2^q points, natural order in and out: radix-2
+// decimation-in-frequency stages, then the bit-reversal as register renaming.
+template <int R, int S>
+__device__ __forceinline__ void dif_stage(float2* v) {
+#pragma unroll
+  for (int blk = 0; blk < R; blk += 2 * S) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const float2 a = v[blk + k], b = v[blk + k + S];
+      v[blk + k] = cadd(a, b);
+      const float2 d = csub(a, b);
+      // W_{2S}^k = W_16^{k 16 / (2S)}
+      constexpr int step = 16 / (2 * S);
+      switch (k * step) {
+        case 0: v[blk + k + S] = d; break;
+        case 1: v[blk + k + S] = rot16<1>(d); break;
+        case 2: v[blk + k + S] = rot16<2>(d); break;
+        case 3: v[blk + k + S] = rot16<3>(d); break;
+        case 4: v[blk + k + S] = rot16<4>(d); break;
+        case 5: v[blk + k + S] = rot16<5>(d); break;
+        case 6: v[blk + k + S] = rot16<6>(d); break;
+        default: v[blk + k + S] = rot16<7>(d); break;
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R >= 16) dif_stage<R, 8>(v);
+  if constexpr (R >= 8) dif_stage<R, 4>(v);
+  if constexpr (R >= 4) dif_stage<R, 2>(v);
+  if constexpr (R >= 2) dif_stage<R, 1>(v);
+  float2 t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) t[r] = v[bitrev<R>(r)];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = t[r];
+}
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+template <int LOG2N>
+struct Fft {
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int E = N < 16 ? N : 16;  // samples per lane
+  static constexpr int T = N / E;            // lanes per row
+  static constexpr int RPW = kThreads / T;   // rows per workgroup
+  static constexpr int PADN = N + N / 16;    // padded LDS row
+};
+
+// One Stockham pass of radix R at stride NS over the E samples of this lane
+// (E / R butterflies b = j + T u).
+template <int LOG2N, int R, int NS, bool FIRST, bool LAST>
+__device__ __forceinline__ void fft_pass(const RangeArgs& a, float2* buf, int j, const float2* src, bool live) {
+  using F = Fft<LOG2N>;
+  constexpr int N = F::N, E = F::E, T = F::T, B = E / R;
+  float2 v[E];
+  float2 w[E];
+  if constexpr (NS > 1) {
+    constexpr int lg = __builtin_ctz(NS * R);
+    const int sh = a.tw_log2 - lg;
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int b = j + T * u;
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[u * R + r] = a.twiddle[((b & (NS - 1)) * r) << sh];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int b = j + T * u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = b + r * (N / R);
+      if constexpr (FIRST) {
+        float2 x = make_float2(0.f, 0.f);
+        if (live && i < a.n_s) {
+          const float2 z = src[i];
+          const float wr = a.w_range[i];
+          x = make_float2(z.x * wr, z.y * wr);
+        }
+        v[u * R + r] = x;
+      } else {
+        v[u * R + r] = buf[pad(i)];
+      }
+    }
+  }
+  if constexpr (!FIRST) __syncthreads();  // every read of this pass precedes its writes
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], w[u * R + r]);
+    }
+    dft<R>(v + u * R);
+  }
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int b = j + T * u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (LAST) {
+        const int k = b + r * NS;  // natural order after the last pass
+        if (k < a.n_bins) buf[pad(k)] = v[u * R + r];
+      } else {
+        const int i = (b / NS) * NS * R + (b & (NS - 1)) + r * NS;
+        buf[pad(i)] = v[u * R + r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int LOG2N>
+__global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeArgs a) {
+  using F = Fft<LOG2N>;
+  __shared__ float2 lds[F::RPW * F::PADN];
+  const int lrow = threadIdx.x / F::T;
+  const int j = threadIdx.x - lrow * F::T;
+  const int64_t row = (int64_t)blockIdx.x * F::RPW + lrow;
   const bool live = row < a.rows;
-  float2* buf = lds + (size_t)lrow * n;
+  float2* buf = lds + lrow * F::PADN;
+  const float2* src = a.raw + (live ? row : 0) * a.n_s;
 
-  // zero-padding: clear the row buffer, then scatter the windowed samples to
-  // their bit-reversed positions
-  for (int k = t; k < n; k += tpr) buf[k] = make_float2(0.f, 0.f);
-  __syncthreads();
-  if (live) {
-    const float2* src = a.raw + row * a.n_s;
-    const int sh = 32 - a.log2n;
-    for (int k = t; k < a.n_s; k += tpr) {
-      const float2 x = src[k];
-      const float w = a.w_range[k];
-      buf[__builtin_bitreverse32((unsigned)k) >> sh] = make_float2(x.x * w, x.y * w);
-    }
-  }
-  __syncthreads();
-
-  // odd log2(n): one size-2 stage (twiddle 1)
-  int h = 1;
-  if (a.log2n & 1) {
-    for (int g = t; g < n / 2; g += tpr) {
-      const float2 u = buf[2 * g], v = buf[2 * g + 1];
-      buf[2 * g] = cadd(u, v);
-      buf[2 * g + 1] = csub(u, v);
-    }
-    h = 2;
-    __syncthreads();
-  }
-  // pairs of stages: sizes 2h (half h) and 4h (half 2h)
-  for (; h < n; h *= 4) {
-    const int shA = a.tw_log2 - __builtin_ctz(2 * h);  // W_{2h}^j = tw[j << shA]
-    const int shB = a.tw_log2 - __builtin_ctz(4 * h);  // W_{4h}^j = tw[j << shB]
-    for (int g = t; g < n / 4; g += tpr) {
-      const int j = g & (h - 1);
-      const int base = (g - j) * 4 + j;
-      const float2 wA = a.twiddle[j << shA];
-      const float2 wB = a.twiddle[j << shB];
-      const float2 x0 = buf[base], x1 = buf[base + h], x2 = buf[base + 2 * h], x3 = buf[base + 3 * h];
-      const float2 t1 = cmul(wA, x1), t3 = cmul(wA, x3);
-      const float2 b0 = cadd(x0, t1), b1 = csub(x0, t1);
-      const float2 b2 = cadd(x2, t3), b3 = csub(x2, t3);
-      const float2 u2 = cmul(wB, b2);
-      const float2 u3 = cmul_mi(cmul(wB, b3));            // W_{4h}^{j+h} = -i W_{4h}^j
-      buf[base] = cadd(b0, u2);
-      buf[base + 2 * h] = csub(b0, u2);
-      buf[base + h] = cadd(b1, u3);
-      buf[base + 3 * h] = csub(b1, u3);
-    }
-    __syncthreads();
+  if constexpr (LOG2N < 4) {
+    fft_pass<LOG2N, F::N, 1, true, true>(a, buf, j, src, live);
+  } else {
+    constexpr int P16 = LOG2N / 4, REM = LOG2N % 4;
+    fft_pass<LOG2N, 16, 1, true, P16 == 1 && REM == 0>(a, buf, j, src, live);
+    if constexpr (P16 >= 2) fft_pass<LOG2N, 16, 16, false, P16 == 2 && REM == 0>(a, buf, j, src, live);
+    if constexpr (P16 >= 3) fft_pass<LOG2N, 16, 256, false, REM == 0>(a, buf, j, src, live);
+    if constexpr (REM > 0) fft_pass<LOG2N, (1 << REM), (1 << (4 * P16)), false, true>(a, buf, j, src, live);
   }
 
   if (!live) return;
@@ -90,12 +195,21 @@ __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeArgs a, i
   float4* dst = a.pairs + row * a.n_bins;
   float2* spec = a.spectrum ? a.spectrum + row * a.n_bins : nullptr;
   const int last = a.n_bins - 1;
-  for (int k = t; k < a.n_bins; k += tpr) {
-    const float2 x = buf[k];
-    const float2 d = (k < last) ? csub(buf[k + 1], x) : make_float2(0.f, 0.f);
+  for (int k = j; k < a.n_bins; k += F::T) {
+    const float2 x = buf[pad(k)];
+    const float2 d = (k < last) ? csub(buf[pad(k + 1)], x) : make_float2(0.f, 0.f);
     dst[k] = make_float4(w * x.x, w * x.y, w * d.x, w * d.y);
     if (spec) spec[k] = x;
   }
+}
+
+template <int LOG2N>
+hipError_t launch_fft(const RangeArgs& a, hipStream_t s) {
+  using F = Fft<LOG2N>;
+  const int64_t grid = (a.rows + F::RPW - 1) / F::RPW;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(range_compress_kernel<LOG2N>, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kThreads) void spectrum_pairs_kernel(PairArgs a) {
@@ -118,14 +232,19 @@ hipError_t launch_range_compress(const RangeArgs& a, hipStream_t s) {
       a.n_s < 1 || a.n_s > a.n_fft || a.n_bins < 1 || a.n_bins > a.n_fft || a.n_ch < 1 ||
       a.tw_log2 < a.log2n || a.tw_log2 > 12)
     return hipErrorInvalidValue;
-  int tpr = a.n_fft / 4;
-  if (tpr > kThreads) tpr = kThreads;
-  const int rows_per_wg = kThreads / tpr;
-  const int64_t grid = (a.rows + rows_per_wg - 1) / rows_per_wg;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t lds = (size_t)rows_per_wg * a.n_fft * sizeof(float2);
-  hipLaunchKernelGGL(range_compress_kernel, dim3((unsigned)grid), dim3(kThreads), lds, s, a, tpr);
-  return hipGetLastError();
+  switch (a.log2n) {
+    case 2: return launch_fft<2>(a, s);
+    case 3: return launch_fft<3>(a, s);
+    case 4: return launch_fft<4>(a, s);
+    case 5: return launch_fft<5>(a, s);
+    case 6: return launch_fft<6>(a, s);
+    case 7: return launch_fft<7>(a, s);
+    case 8: return launch_fft<8>(a, s);
+    case 9: return launch_fft<9>(a, s);
+    case 10: return launch_fft<10>(a, s);
+    case 11: return launch_fft<11>(a, s);
+    default: return launch_fft<12>(a, s);
+  }
 }
 
 hipError_t launch_spectrum_pairs(const PairArgs& a, hipStream_t s) {

@@ -21,7 +21,7 @@ struct RangeArgs {
   const float2* raw;      // [rows][n_s]
   const float* w_range;   // [n_s]
   const float* w_sar;     // [n_chirps]
-  const float2* twiddle;  // [n_fft_max / 2], exp(-2 pi i k / n_fft_max)
+  const float2* twiddle;  // [n_fft_max], exp(-2 pi i k / n_fft_max)
   int tw_log2;            // log2(n_fft_max)
   float4* pairs;          // [rows][n_bins]
   float2* spectrum;       // [rows][n_bins] or nullptr
@@ -75,7 +75,10 @@ hipError_t launch_pixel_tables(const TableArgs& a, hipStream_t s);
 // |P|^2 + |q|^2 - 2 P.q from per-row uniforms.
 //
 // A launch processes a batch of frames that share chg and the precision form.
-// Work items are (frame, chirp block, 16 x 16 pixel tile); a frame too small
+// Work items are (frame, chirp block, 16 x 16 pixel tile); every frame is
+// spread over all eight XCDs, each XCD taking a contiguous eighth of its
+// items (so one frame's neighbouring tiles share that XCD's L2 while the
+// frames of a batch stay balanced over the XCDs); a frame too small
 // to fill the GPU splits its chirp sum into n_kb blocks whose partial images
 // are summed afterwards in block order (reduce_partials), so every frame's
 // result depends only on its own sizes, never on the rest of the batch.
@@ -95,7 +98,9 @@ struct BpFrame {
   int n_rows, n_cols;
   int n_kb;               // chirp blocks
   int tiles_x, n_tiles;   // workgroup tiles per chirp block
-  int item_base;          // first work item of this frame in the launch
+  // each XCD takes a contiguous chunk of ceil(n_kb n_tiles / 8) of the frame's
+  // items; slot_base is the frame's first per-XCD slot in the launch
+  int chunk, slot_base;
   float a1;               // bins per wavelength of two-way path
   // bounding boxes of all TX / RX positions (wavelengths, local frame) and
   // the index margin that lets a wave skip the per-term range test when every
@@ -111,7 +116,7 @@ constexpr int kBpMaxFrames = 16;  // frames per launch (descriptors travel as ke
 enum BpForm { kBpPlain = 0, kBpSplit = 1, kBpExact = 2 };
 
 struct BpBatch {
-  int chg, form, n_frames, n_items;
+  int chg, form, n_frames, n_slots;  // n_slots: per-XCD slots (grid = 8 n_slots)
   BpFrame f[kBpMaxFrames];
 };
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s);
@@ -146,8 +151,54 @@ struct CfarArgs {
   unsigned long long* mask;  // [n_rows][words_per_row]
   int words_per_row;
   rc_detection* det_cell;    // [n_rows * n_cols]
+  // near-threshold cells are appended to listed[0, recheck_cap) (count in
+  // *n_listed, which may exceed the capacity) for the double-precision
+  // recheck; recheck_cap == 0 only flags them RC_DET_NEAR_THRESHOLD
+  int* listed;
+  int* n_listed;
+  int recheck_cap;
 };
 hipError_t launch_cfar(const CfarArgs& a, hipStream_t s);
+
+// Double-precision recheck of the listed cells (see recheck.hip).
+struct RecheckArgs {
+  const int* listed;
+  const int* n_listed;
+  int cap;
+  int n_rows, n_cols, half, guard;   // half = guard + train
+  double alpha_over_n;
+  const float2* pix;        // pixel positions (metres)
+  const float4* geo;        // [rows]: (q_tx.x, q_tx.y, q_rx.x, q_rx.y), metres
+  const float2* vel;        // [n_chirps] velocity (exact form)
+  const double2* spec;      // [rows][n_bins] beat spectrum in double
+  const double* w_sar;      // [n_chirps] chirp window in double
+  int n_chirps, n_ch, n_bins, exact;
+  double a1;                // bins per metre of two-way path
+  double kd;                // bins per m/s of radial speed
+  double inv_lam;           // turns per metre of path
+  double qt_x, qt_y, qr_x, qr_y, v_x, v_y;  // aperture centre and mean velocity (Doppler table)
+  double* power;            // [cap][(2 half + 1)^2] scratch
+  unsigned long long* mask;
+  int words_per_row;
+  rc_detection* det_cell;
+};
+hipError_t launch_recheck(const RecheckArgs& a, hipStream_t s);
+
+// Beat spectrum in double for the recheck: from the raw cube by a double FFT
+// (raw != nullptr) or widened from a complex64 spectrum input.
+struct Range64Args {
+  const float2* raw;          // [rows][n_s] or nullptr
+  const float2* spectrum_in;  // [rows][n_bins] when raw == nullptr
+  const double* w_range;      // [n_s]
+  const double2* twiddle;     // exp(-2 pi i k / 2^tw_log2), k < 2^(tw_log2 - 1)
+  int tw_log2;
+  double2* spec;              // [rows][n_bins]
+  int64_t rows;
+  int n_s, n_fft, log2n, n_bins;
+};
+hipError_t launch_range64(const Range64Args& a, hipStream_t s);
+// *count = 0 by a one-lane kernel (stream-ordered, capturable)
+hipError_t launch_clear_count(int* count, hipStream_t s);
 
 // Ordered compaction of the detection mask into det_out[0, cap) and count.
 struct CompactArgs {

@@ -60,7 +60,8 @@ double bessel_i0(double x) {
   return sum;
 }
 
-void make_window(rc_window_kind kind, double beta, int n, float* out) {
+template <class T>
+void make_window(rc_window_kind kind, double beta, int n, T* out) {
   for (int t = 0; t < n; ++t) {
     double w = 1.0;
     if (n > 1 && kind == RC_WIN_HANN) {
@@ -69,7 +70,7 @@ void make_window(rc_window_kind kind, double beta, int n, float* out) {
       const double u = 2.0 * t / (n - 1) - 1.0;
       w = bessel_i0(beta * std::sqrt(std::max(0.0, 1.0 - u * u))) / bessel_i0(beta);
     }
-    out[t] = (float)w;
+    out[t] = (T)w;
   }
 }
 
@@ -87,6 +88,11 @@ struct Slot {
   rc_detection* det_cell = nullptr;
   rc_detection* det_out = nullptr;
   int64_t* det_count = nullptr;
+  int* listed = nullptr;      // near-threshold cells for the double-precision recheck
+  int* n_listed = nullptr;
+  double* rpower = nullptr;   // recomputed window powers of the listed cells
+  double2* spec64 = nullptr;  // beat spectrum in double for the recheck
+  rc::RecheckArgs rk{};       // geometry part filled by prepare_frame
   // pinned host
   float* staging = nullptr;
   int64_t* h_count = nullptr;
@@ -104,17 +110,24 @@ struct Plan {
   rc_plan_desc d;
   int device = 0;
   float2* twiddle = nullptr;
+  double2* twiddle64 = nullptr;  // with the recheck on
   int tw_log2 = 0;
   size_t geo_floats = 0;  // floats of the staging/rowgeo region
   std::vector<Slot> slots;
 };
 
 struct SlotSizes {
-  size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out;
+  size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out, listed, rpower, spec64;
   size_t total() const {
-    return pairs + geo + fd + pixc + fbase + partials + image + mask + det_cell + det_out + 64;
+    return pairs + geo + fd + pixc + fbase + partials + image + mask + det_cell + det_out + listed + rpower +
+           spec64 + 64;
   }
 };
+
+int window_cells(const rc_plan_desc& d) {
+  const int w = 2 * (d.cfar_guard + d.cfar_train) + 1;
+  return w * w;
+}
 
 size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -125,11 +138,17 @@ int64_t partial_capacity(const rc_plan_desc& d) {
   return std::min<int64_t>(16 * d.n_pix_max, (int64_t(1) << 20) + d.n_pix_max);
 }
 
-// staging/device geometry region: rowq[rows] and grpq[rows] float4, then
-// w_sar[n_chirps_max] and w_range[n_samples_max]
+// staging/device geometry region: rowq[rows] and grpq[rows] float4; with the
+// recheck on, the antenna positions in metres (q_tx, q_rx) float4[rows], the
+// velocities float2[n_chirps] and the windows in double, w_sar[n_chirps] and
+// w_range[n_samples]; then the windows in single precision
+size_t recheck_floats(int64_t rows, int64_t n_chirps, int64_t n_samples) {
+  return 4 * rows + 2 * n_chirps + 2 * n_chirps + 2 * n_samples;
+}
 size_t geo_floats(const rc_plan_desc& d) {
   const size_t rows = (size_t)d.n_chirps_max * d.n_channels_max;
-  return rows * 8 + d.n_chirps_max + d.n_samples_max;
+  const size_t metres = d.max_rechecks > 0 ? recheck_floats(rows, d.n_chirps_max, d.n_samples_max) : 0;
+  return rows * 8 + metres + d.n_chirps_max + d.n_samples_max;
 }
 
 SlotSizes slot_sizes(const rc_plan_desc& d) {
@@ -145,6 +164,9 @@ SlotSizes slot_sizes(const rc_plan_desc& d) {
   s.mask = round_up((size_t)d.n_pix_max * sizeof(unsigned long long));
   s.det_cell = round_up((size_t)d.n_pix_max * sizeof(rc_detection));
   s.det_out = round_up((size_t)d.max_detections * sizeof(rc_detection));
+  s.listed = round_up((size_t)d.max_rechecks * sizeof(int));
+  s.rpower = round_up((size_t)d.max_rechecks * window_cells(d) * sizeof(double));
+  s.spec64 = d.max_rechecks > 0 ? round_up(rows * d.n_bins_max * sizeof(double2)) : 0;
   return s;
 }
 
@@ -170,6 +192,8 @@ rc_status validate_desc(const rc_plan_desc* d) {
     return fail(RC_EINVAL, "need guard >= 0, train >= 1, guard + train <= 16");
   if (!(d->cfar_pfa > 0 && d->cfar_pfa < 1)) return fail(RC_EINVAL, "cfar_pfa must be in (0, 1)");
   if (d->cfar_margin_rel < 0) return fail(RC_EINVAL, "cfar_margin_rel must be >= 0");
+  if (d->max_rechecks < 0 || d->max_rechecks > (1 << 20))
+    return fail(RC_EINVAL, "max_rechecks must be in [0, 2^20]");
   if (d->precision != RC_PREC_FP32 && d->precision != RC_PREC_FP32_SPLIT)
     return fail(RC_EINVAL, "unknown precision %d", (int)d->precision);
   if (d->doppler != RC_DOPPLER_AVERAGE && d->doppler != RC_DOPPLER_EXACT)
@@ -196,6 +220,7 @@ void free_plan(Plan* p) {
   if (!p) return;
   for (Slot& s : p->slots) free_slot(s);
   if (p->twiddle) (void)hipFree(p->twiddle);
+  if (p->twiddle64) (void)hipFree(p->twiddle64);
   delete p;
 }
 
@@ -325,16 +350,29 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   }
   vx /= f.n_chirps;
   vy /= f.n_chirps;
-  float* w_sar = g + 8 * rows;
+  const bool recheck = d.max_rechecks > 0;
+  const int n_s = f.input_kind == RC_INPUT_RAW ? f.n_samples : 0;
+  const int64_t metres = recheck ? (int64_t)recheck_floats(rows, f.n_chirps, n_s) : 0;
+  float4* geo_m = rowq + 2 * rows;
+  float2* vel_m = reinterpret_cast<float2*>(geo_m + rows);
+  double* w_sar64 = reinterpret_cast<double*>(vel_m + f.n_chirps);
+  double* w_range64 = w_sar64 + f.n_chirps;
+  if (recheck) {
+    for (int64_t r = 0; r < rows; ++r)
+      geo_m[r] = make_float4(f.q_tx[2 * r], f.q_tx[2 * r + 1], f.q_rx[2 * r], f.q_rx[2 * r + 1]);
+    for (int m = 0; m < f.n_chirps; ++m) vel_m[m] = make_float2(f.vel[2 * m], f.vel[2 * m + 1]);
+    make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar64);
+    make_window(d.range_window, d.range_kaiser_beta, n_s, w_range64);
+  }
+  float* w_sar = g + 8 * rows + metres;
   make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
   float* w_range = w_sar + f.n_chirps;
-  const int n_s = f.input_kind == RC_INPUT_RAW ? f.n_samples : 0;
   make_window(d.range_window, d.range_kaiser_beta, n_s, w_range);
-  const size_t geo_bytes = (size_t)(8 * rows + f.n_chirps + n_s) * sizeof(float);
+  const size_t geo_bytes = (size_t)(8 * rows + metres + f.n_chirps + n_s) * sizeof(float);
   RC_HIP(hipMemcpyAsync(s.rowgeo, s.staging, geo_bytes, hipMemcpyHostToDevice, st));
   const float4* d_rowq = s.rowgeo;
   const float4* d_grpq = s.rowgeo + rows;
-  const float* d_wsar = reinterpret_cast<const float*>(s.rowgeo) + 8 * rows;
+  const float* d_wsar = reinterpret_cast<const float*>(s.rowgeo) + 8 * rows + metres;
   const float* d_wrange = d_wsar + f.n_chirps;
   const bool timed = d.stage_timing != 0;
   if (timed) RC_HIP(hipEventRecord(s.stage_ev[0], st));
@@ -361,6 +399,25 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
     RC_HIP(rc::launch_spectrum_pairs(pa, st));
   }
 
+  if (recheck) {
+    // the recheck's beat spectrum in double (same input, double arithmetic);
+    // the double windows follow the velocities in the geometry region
+    const double* d_wsar64 = reinterpret_cast<const double*>(reinterpret_cast<const float2*>(s.rowgeo + 3 * rows) + f.n_chirps);
+    const bool raw_in = f.input_kind == RC_INPUT_RAW;
+    rc::Range64Args r6{};
+    r6.raw = raw_in ? static_cast<const float2*>(f.data) : nullptr;
+    r6.spectrum_in = raw_in ? nullptr : static_cast<const float2*>(f.data);
+    r6.w_range = d_wsar64 + f.n_chirps;
+    r6.twiddle = p->twiddle64;
+    r6.tw_log2 = p->tw_log2;
+    r6.spec = s.spec64;
+    r6.rows = rows;
+    r6.n_s = n_s;
+    r6.n_fft = raw_in ? f.n_fft : 0;
+    r6.log2n = raw_in ? ilog2(f.n_fft) : 0;
+    r6.n_bins = f.n_bins;
+    RC_HIP(rc::launch_range64(r6, st));
+  }
   if (timed) RC_HIP(hipEventRecord(s.stage_ev[1], st));
 
   // 2. per-frame tables: Doppler (Sec. III-D) and local pixel coordinates
@@ -415,6 +472,26 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   if (n_kb > 1 && (int64_t)n_kb * n_pix > s.partial_cap)
     return fail(RC_EINVAL, "frame %lld: %d chirp blocks of %lld pixels exceed the slot's partial buffer",
                 (long long)f.frame_id, n_kb, (long long)n_pix);
+  // geometry of the double-precision recheck (metres, Alg. 2 or Alg. 1)
+  rc::RecheckArgs& rk = s.rk;
+  rk = rc::RecheckArgs{};
+  if (recheck) {
+    rk.pix = pix;
+    rk.geo = s.rowgeo + 2 * rows;
+    rk.vel = reinterpret_cast<const float2*>(s.rowgeo + 3 * rows);
+    rk.spec = s.spec64;
+    rk.w_sar = reinterpret_cast<const double*>(rk.vel + f.n_chirps);
+    rk.n_chirps = f.n_chirps;
+    rk.n_ch = f.n_channels;
+    rk.n_bins = f.n_bins;
+    rk.exact = exact;
+    rk.a1 = a1;
+    rk.kd = kd;
+    rk.inv_lam = inv_lam;
+    rk.qt_x = ta.qt_x; rk.qt_y = ta.qt_y;
+    rk.qr_x = ta.qr_x; rk.qr_y = ta.qr_y;
+    rk.v_x = vx; rk.v_y = vy;
+  }
   *chg_out = chg;
   s.busy = true;
   s.frame_id = f.frame_id;
@@ -435,9 +512,28 @@ rc_status finish_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
   const int n_train = (2 * h + 1) * (2 * h + 1) - (2 * d.cfar_guard + 1) * (2 * d.cfar_guard + 1);
   const double alpha = n_train * (std::pow(d.cfar_pfa, -1.0 / n_train) - 1.0);
   const int wpr = (f.n_cols + 63) / 64;
+  const bool recheck = d.max_rechecks > 0;
+  if (recheck) RC_HIP(rc::launch_clear_count(s.n_listed, st));
   rc::CfarArgs ca{img, f.n_rows, f.n_cols, d.cfar_guard, d.cfar_train, alpha / n_train,
-                  d.cfar_margin_rel, s.mask, wpr, s.det_cell};
+                  d.cfar_margin_rel, s.mask, wpr, s.det_cell,
+                  s.listed, s.n_listed, recheck ? d.max_rechecks : 0};
   RC_HIP(rc::launch_cfar(ca, st));
+  if (recheck) {
+    rc::RecheckArgs rk = s.rk;
+    rk.listed = s.listed;
+    rk.n_listed = s.n_listed;
+    rk.cap = d.max_rechecks;
+    rk.n_rows = f.n_rows;
+    rk.n_cols = f.n_cols;
+    rk.half = h;
+    rk.guard = d.cfar_guard;
+    rk.alpha_over_n = alpha / n_train;
+    rk.power = s.rpower;
+    rk.mask = s.mask;
+    rk.words_per_row = wpr;
+    rk.det_cell = s.det_cell;
+    RC_HIP(rc::launch_recheck(rk, st));
+  }
   rc::CompactArgs pa{s.mask, s.det_cell, f.n_rows, f.n_cols, wpr, s.det_out,
                      (int64_t)d.max_detections, s.det_count};
   RC_HIP(rc::launch_compact(pa, st));
@@ -469,8 +565,9 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
   if (st != RC_OK) return st;
   const SlotSizes sz = slot_sizes(*desc);
   const size_t per_slot = sz.total();
-  const size_t tw_bytes = (size_t)desc->n_fft_max / 2 * sizeof(float2);
-  const size_t need = per_slot * desc->max_frames_in_flight + tw_bytes;
+  const size_t tw_bytes = (size_t)desc->n_fft_max * sizeof(float2);
+  const size_t tw64_bytes = desc->max_rechecks > 0 ? (size_t)desc->n_fft_max / 2 * sizeof(double2) : 0;
+  const size_t need = per_slot * desc->max_frames_in_flight + tw_bytes + tw64_bytes;
   if (desc->hbm_budget_bytes > 0 && need > (size_t)desc->hbm_budget_bytes)
     return fail(RC_ENOMEM, "plan needs %zu bytes of device memory, budget is %lld", need,
                 (long long)desc->hbm_budget_bytes);
@@ -483,16 +580,26 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     delete p;
     return fail(RC_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
   }
-  // twiddles exp(-2 pi i k / n_fft_max), k < n_fft_max / 2, evaluated in double
+  // twiddles exp(-2 pi i k / n_fft_max) over the full circle (single
+  // precision) and the half circle (double, for the recheck), evaluated in double
   p->tw_log2 = ilog2(desc->n_fft_max);
   {
-    std::vector<float2> tw(desc->n_fft_max / 2);
+    std::vector<float2> tw(desc->n_fft_max);
     for (size_t k = 0; k < tw.size(); ++k) {
       const double a = -2.0 * kPi * (double)k / desc->n_fft_max;
       tw[k] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
     e = hipMalloc(&p->twiddle, tw_bytes);
     if (e == hipSuccess) e = hipMemcpy(p->twiddle, tw.data(), tw_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && desc->max_rechecks > 0) {
+      std::vector<double2> tw64(desc->n_fft_max / 2);
+      for (size_t k = 0; k < tw64.size(); ++k) {
+        const double a = -2.0 * kPi * (double)k / desc->n_fft_max;
+        tw64[k] = make_double2(std::cos(a), std::sin(a));
+      }
+      e = hipMalloc(&p->twiddle64, tw64_bytes);
+      if (e == hipSuccess) e = hipMemcpy(p->twiddle64, tw64.data(), tw64_bytes, hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
       free_plan(p);
       return fail(e == hipErrorOutOfMemory ? RC_ENOMEM : RC_EHIP, "twiddle table: %s", hipGetErrorString(e));
@@ -521,7 +628,11 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     s.mask = reinterpret_cast<unsigned long long*>(take(sz.mask));
     s.det_cell = reinterpret_cast<rc_detection*>(take(sz.det_cell));
     s.det_out = reinterpret_cast<rc_detection*>(take(sz.det_out));
+    s.listed = sz.listed ? reinterpret_cast<int*>(take(sz.listed)) : nullptr;
+    s.rpower = sz.rpower ? reinterpret_cast<double*>(take(sz.rpower)) : nullptr;
+    s.spec64 = sz.spec64 ? reinterpret_cast<double2*>(take(sz.spec64)) : nullptr;
     s.det_count = reinterpret_cast<int64_t*>(take(64));
+    s.n_listed = reinterpret_cast<int*>(s.det_count + 1);
     e = hipHostMalloc(reinterpret_cast<void**>(&s.staging), geo_bytes, hipHostMallocDefault);
     if (e == hipSuccess) {
       const size_t hb = 64 + (size_t)std::min(kDetPrefix, desc->max_detections) * sizeof(rc_detection);
@@ -579,20 +690,31 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   const bool timed = p->d.stage_timing != 0;
   if (timed)
     for (Slot* q : slot) RC_HIP(hipEventRecord(q->stage_ev[2], st));
-  // 3: back-projection, one launch per TX-group width and per 16 frames
+  // 3: back-projection, one launch per TX-group width and per 16 frames; the
+  // frames of a launch go most expensive work item first (fewest short items
+  // in the tail)
+  std::vector<int> order(n_frames);
+  for (int i = 0; i < n_frames; ++i) order[i] = i;
+  auto item_cost = [&](int i) {
+    return (int64_t)((bpf[i].n_chirps + bpf[i].n_kb - 1) / bpf[i].n_kb) * bpf[i].n_ch;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return item_cost(x) > item_cost(y); });
   std::vector<char> done(n_frames, 0);
-  for (int i = 0; i < n_frames; ++i) {
+  for (int oi = 0; oi < n_frames; ++oi) {
+    const int i = order[oi];
     if (done[i]) continue;
     rc::BpBatch b{};
     b.chg = chg[i];
     b.form = p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
              : p->d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
-    for (int j = i; j < n_frames && b.n_frames < rc::kBpMaxFrames; ++j) {
+    for (int oj = oi; oj < n_frames && b.n_frames < rc::kBpMaxFrames; ++oj) {
+      const int j = order[oj];
       if (done[j] || chg[j] != chg[i]) continue;
       rc::BpFrame fj = bpf[j];
-      fj.item_base = b.n_items;
+      fj.chunk = (fj.n_kb * fj.n_tiles + 7) / 8;
+      fj.slot_base = b.n_slots;
       b.f[b.n_frames++] = fj;
-      b.n_items += fj.n_kb * fj.n_tiles;
+      b.n_slots += fj.chunk;
       done[j] = 1;
     }
     hipError_t e = rc::launch_backproject(b, st);

@@ -32,6 +32,7 @@ RC_DOPPLER_AVERAGE, RC_DOPPLER_EXACT = 0, 1
 # rc_input_kind
 RC_INPUT_RAW, RC_INPUT_SPECTRUM = 0, 1
 RC_DET_NEAR_THRESHOLD = 1
+RC_DET_RECHECKED = 2
 
 
 class rc_radar(C.Structure):
@@ -61,6 +62,7 @@ class rc_plan_desc(C.Structure):
         ("cfar_train", C.c_int32),
         ("cfar_pfa", C.c_double),
         ("cfar_margin_rel", C.c_double),
+        ("max_rechecks", C.c_int32),
         ("hbm_budget_bytes", C.c_int64),
         ("stage_timing", C.c_int32),
     ]
@@ -208,6 +210,7 @@ class PlanConfig:
     cfar_train: int = 8
     cfar_pfa: float = 1e-4
     cfar_margin_rel: float = 3e-2
+    max_rechecks: int = 0
     hbm_budget_bytes: int = 0
     stage_timing: bool = False
 
@@ -219,7 +222,7 @@ class PlanConfig:
             self.n_channels_max, self.n_pix_max, self.max_frames_in_flight, self.max_detections,
             WINDOWS[self.range_window], self.range_kaiser_beta, WINDOWS[self.sar_window],
             self.sar_kaiser_beta, self.precision, self.doppler, self.cfar_guard, self.cfar_train, self.cfar_pfa,
-            self.cfar_margin_rel, self.hbm_budget_bytes, int(self.stage_timing))
+            self.cfar_margin_rel, self.max_rechecks, self.hbm_budget_bytes, int(self.stage_timing))
 
 
 def slot_bytes(cfg: PlanConfig) -> int:

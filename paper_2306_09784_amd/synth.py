@@ -97,6 +97,10 @@ CONFIGS = {
     "paper-polar": SceneConfig("paper-polar", n_samples=1024, n_chirps=1024, n_tx=1, n_rx=8,
                                box=(-15.0, 15.0, 1.0, 31.0), nx=1201, ny=1201, speed=1.2,
                                n_targets=64, snr_db=(0.0, 30.0), n_clutter=3, seed=1002),
+    # the paper's reference setting (Sec. II, Tab. I): one TX, 16 RX, 1024 chirps
+    "paper-ref": SceneConfig("paper-ref", n_samples=1024, n_chirps=1024, n_tx=1, n_rx=16,
+                             box=(-15.0, 15.0, 1.0, 31.0), nx=1201, ny=1201, speed=1.2,
+                             n_targets=64, snr_db=(0.0, 30.0), n_clutter=3, seed=1002),
 }
 
 

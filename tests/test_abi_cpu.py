@@ -53,7 +53,7 @@ int main(void) {
          sizeof(rc_radar), sizeof(rc_plan_desc), sizeof(rc_frame), sizeof(rc_detection));
   P(rc_plan_desc, radar) P(rc_plan_desc, n_pix_max) P(rc_plan_desc, range_window)
   P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision) P(rc_plan_desc, doppler)
-  P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
+  P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, max_rechecks) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
   P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
   P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out)
   P(rc_detection, threshold) P(rc_detection, flags)
@@ -94,12 +94,16 @@ def test_descriptor_validation(rc):
     bad = [dict(n_fft_max=500), dict(n_fft_max=8192, n_samples_max=256), dict(n_bins_max=1024),
            dict(n_samples_max=1024), dict(cfar_guard=10, cfar_train=10), dict(cfar_pfa=1.5),
            dict(max_frames_in_flight=0), dict(precision=7), dict(range_window="bogus"), dict(doppler=5),
-           dict(doppler=1, precision=1)]
+           dict(doppler=1, precision=1), dict(max_rechecks=-1), dict(max_rechecks=(1 << 20) + 1)]
     for kw in bad:
         with pytest.raises((rc.RcError, KeyError)) as ei:
             rc.slot_bytes(_cfg(rc, **kw))
         if isinstance(ei.value, rc.RcError):
             assert ei.value.status == rc.RC_EINVAL, kw
+    # the recheck adds the double spectrum (16 B/bin), the cell list and the
+    # window powers (441 doubles per listed cell)
+    extra = rc.slot_bytes(_cfg(rc, max_rechecks=1000)) - good
+    assert extra >= 128 * 4 * 256 * 16 + 1000 * (4 + 441 * 8)
     d = _cfg(rc).desc()
     d.abi_version = 99
     h = C.c_void_p()

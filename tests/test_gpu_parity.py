@@ -121,6 +121,45 @@ def test_range_and_doppler_parity_plain_small(rc, torch):
     _check_image("image_small_64x48", fr, out["image"], ora, PLAIN)
 
 
+@pytest.mark.parametrize("log2n,n_s,n_bins", [(2, 3, 4), (3, 8, 5), (4, 9, 16), (5, 32, 7), (6, 40, 33),
+                                                (7, 64, 27), (8, 200, 256), (9, 256, 101), (10, 1000, 433),
+                                                (11, 1024, 432), (12, 2048, 900), (12, 4096, 2)])
+def test_range_parity_every_fft_size(rc, torch, log2n, n_s, n_bins):
+    """Range compression alone over every supported DFT length (4 .. 4096),
+    ragged sample counts and kept-bin counts, on 9 rows (not a multiple of
+    the rows a workgroup holds for short rows): the spectrum output against the
+    oracle's FP64 DFT of the same windowed, zero-padded rows."""
+    n_fft = 1 << log2n
+    M, CH = 3, 3
+    rng = np.random.default_rng(1000 + log2n)
+    raw = (rng.standard_normal((M, CH, n_s)) + 1j * rng.standard_normal((M, CH, n_s))).astype(np.complex64)
+    q = np.zeros((M, CH, 2), np.float32)
+    q[..., 0] = np.arange(M * CH, dtype=np.float32).reshape(M, CH) * 1e-3
+    vel = np.zeros((M, 2), np.float32)
+    pix = np.array([[0.0, 5.0], [0.1, 5.0]], np.float32)
+    dev = torch.device("cuda")
+    d_raw = torch.from_numpy(raw).to(dev)
+    d_pix = torch.from_numpy(pix).to(dev)
+    spec = torch.empty((M, CH, n_bins, 2), dtype=torch.float32, device=dev)
+    img = torch.empty((2, 2), dtype=torch.float32, device=dev)
+    cfg = rc.PlanConfig(radar=synth.RADAR, n_samples_max=n_s, n_fft_max=max(n_fft, 4), n_bins_max=max(n_bins, 2),
+                        n_chirps_max=M, n_channels_max=CH, n_pix_max=2, max_frames_in_flight=1)
+    with rc.Plan(cfg) as plan:
+        fr = rc.Plan.make_frame(1, data=d_raw, q_tx=q, q_rx=q, vel=vel, pixels=d_pix, n_rows=1, n_cols=2,
+                                n_bins=n_bins, n_fft=n_fft, fs=1e7, n_samples=n_s, image_out=img, spectrum_out=spec)
+        plan.process([fr])
+        plan.detections(1)
+        torch.cuda.synchronize()
+        got = spec.cpu().numpy().view(np.complex64)[..., 0].astype(np.complex128)
+        plan.release(1)
+    ref = O.range_compress(raw, O.window("hann", n_s), n_fft, n_bins)
+    rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    row_rel = float((np.abs(got - ref).max(-1) / np.abs(ref).max(-1)).max())
+    _report(f"range_n{n_fft}_s{n_s}_b{n_bins}", rel_l2=rel_l2, row_max_rel=row_rel)
+    assert rel_l2 <= SPEC_TOL
+    assert row_rel <= 10 * SPEC_TOL
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("n_tx,n_rx,n_chirps", [(1, 4, 16), (4, 4, 8), (2, 1, 12), (1, 16, 6), (1, 8, 9),
                                                 (1, 2, 10), (1, 1, 1), (3, 1, 5)])
