@@ -52,10 +52,59 @@ def alg2_cost(chg: int):
     return flops, slots
 
 
-def cpu_baseline(frame, budget_s: float = 20.0):
-    """The FP64 oracle on this host: range compression, Doppler table and CFAR
-    over the whole frame, Alg. 2 on a leading slice of pixels, extrapolated
-    linearly in pixels (back-projection is pointwise)."""
+def _kernel_sources_digest() -> str:
+    """sha256 over the back-projection kernel's sources (bp.hip, rc_kernels.hpp)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("bp.hip", "rc_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2306_09784_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per bp_kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a device copy of known size), or None when the summary is missing or
+    was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"bp_kernel_{workload}.traffic.txt")
+    try:
+        with open(path) as f:
+            kv = dict(line.split(None, 1) for line in f if line.strip() and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256", "").strip() != _kernel_sources_digest():
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+
+
+_POOL_ARGS = None
+
+
+def _pool_init(args):
+    global _POOL_ARGS
+    _POOL_ARGS = args
+
+
+def _pool_bp(bounds):
+    """Worker of the process pool: Alg. 2 of the oracle on pixels [lo, hi)."""
+    import oracle as O
+
+    pix, fd, q_tx, q_rx, s, w, a1, a2 = _POOL_ARGS
+    lo, hi = bounds
+    t0 = time.perf_counter()
+    O.bp_alg2(pix[lo:hi], q_tx, q_rx, fd[lo:hi], s, w, a1, a2)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(frame, budget_s: float = 20.0, procs: int = 16):
+    """The FP64 oracle on this host's cores: range compression, Doppler table
+    and CFAR over the whole frame in this process, Alg. 2 on disjoint pixel
+    slices in a pool of single-threaded processes (one per core, at most
+    `procs`), extrapolated linearly in pixels (back-projection is pointwise)."""
+    import multiprocessing as mp
+
     import oracle as O
     from paper_2306_09784_amd import synth
 
@@ -70,31 +119,49 @@ def cpu_baseline(frame, budget_s: float = 20.0):
     t_dop = time.perf_counter() - t0
     w = O.window("hann", frame.cfg.n_chirps)
     n_pix = pix.shape[0]
-    # calibrate a slice that takes about budget_s
+    # calibrate a slice that takes about budget_s on one core
     n = 256
     t0 = time.perf_counter()
     O.bp_alg2(pix[:n], frame.q_tx, frame.q_rx, fd[:n], s, w, k["a1"], k["a2"])
     t_cal = time.perf_counter() - t0
-    n2 = int(min(n_pix, max(n, n * (budget_s - t_cal) / max(t_cal, 1e-3))))
-    t0 = time.perf_counter()
-    O.bp_alg2(pix[n:n + n2], frame.q_tx, frame.q_rx, fd[n:n + n2], s, w, k["a1"], k["a2"])
-    t_bp = time.perf_counter() - t0
-    per_pix = t_bp / n2
+    n2 = int(min(n_pix // max(1, procs), max(n, n * (budget_s - t_cal) / max(t_cal, 1e-3))))
+    P = max(1, min(procs, os.cpu_count() or 1))
+    env_keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {key: os.environ.get(key) for key in env_keys}
+    for key in env_keys:
+        os.environ[key] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        args = (pix, fd, frame.q_tx, frame.q_rx, s, w, k["a1"], k["a2"])
+        with ctx.Pool(P, initializer=_pool_init, initargs=(args,)) as pool:
+            pool.map(_pool_bp, [(0, 8)] * P)  # start-up outside the timed region
+            t0 = time.perf_counter()
+            per_proc = pool.map(_pool_bp, [(n + i * n2, n + (i + 1) * n2) for i in range(P)])
+            t_bp = time.perf_counter() - t0
+    finally:
+        for key, v in saved.items():
+            if v is None:
+                os.environ.pop(key, None)
+            else:
+                os.environ[key] = v
+    pix_per_s = P * n2 / t_bp
     rng = np.random.default_rng(0)
     pw = rng.exponential(1.0, (frame.n_rows, frame.n_cols))
     t0 = time.perf_counter()
     O.ca_cfar(pw, 2, 8, 1e-4)
     t_cfar = time.perf_counter() - t0
-    t_frame = t_range + t_dop + per_pix * n_pix + t_cfar
+    t_frame = t_range + t_dop + n_pix / pix_per_s + t_cfar
+    t_one = t_range + t_dop + n_pix * float(np.mean(per_proc)) / n2 + t_cfar
     return {
         "value": 1.0 / t_frame,
         "unit": "frames/s",
-        "cores": 1,
+        "cores": P,
         "kind": "oracle",
-        "sample": (f"FP64 NumPy oracle, single thread: range DFT of all {frame.cfg.n_chirps * frame.cfg.n_channels} "
-                   f"rows ({t_range:.2f} s), Doppler table ({t_dop:.2f} s), CA-CFAR on a {frame.n_rows}x{frame.n_cols} "
-                   f"lattice ({t_cfar:.2f} s), Alg. 2 on {n2} of {n_pix} pixels ({t_bp:.2f} s) extrapolated "
-                   f"linearly: {t_frame:.0f} s per frame"),
+        "sample": (f"FP64 NumPy oracle: range DFT of all {frame.cfg.n_chirps * frame.cfg.n_channels} rows "
+                   f"({t_range:.2f} s), Doppler table ({t_dop:.2f} s) and CA-CFAR on the {frame.n_rows}x"
+                   f"{frame.n_cols} lattice ({t_cfar:.2f} s) in one process; Alg. 2 on {P} x {n2} of {n_pix} "
+                   f"pixels by {P} single-threaded processes in {t_bp:.1f} s, extrapolated linearly: "
+                   f"{t_frame:.4g} s per frame ({t_one:.4g} s on one core)"),
     }
 
 
@@ -249,7 +316,7 @@ def mixed_plan_config(rc, synth, sensors, slots, **kw):
                          max_detections=1 << 14, **kw)
 
 
-def batched_mixed(rc, synth, torch, sensors, n_frames=64, slots=32):
+def batched_mixed(rc, synth, torch, sensors, n_frames=256, slots=32):
     """Frames of mixed sizes in batches of `slots` frames per rc_process_batch
     (one back-projection launch per TX-group width and 16 frames); each batch
     includes the pinned-memory upload of its beat cubes."""
@@ -294,6 +361,11 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
     return res
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished section (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,7 +373,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain-large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="duration of the Poisson serving run (0 disables it)")
     ap.add_argument("--main-only", action="store_true",
                     help="skip the split-phase, paper-configuration, batched and serving runs")
@@ -346,6 +418,7 @@ def main(argv=None):
                              rc.RC_PREC_FP32, args.steps, args.warmup)
     stages = main_run["stages"]
     n_pix = frame.n_rows * frame.n_cols
+    progress(f"main workload: {main_run['fps']:.1f} frames/s")
 
     M, CH = cfg.n_chirps, cfg.n_channels
     contrib = float(n_pix) * M * CH
@@ -393,7 +466,7 @@ def main(argv=None):
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
         },
         "synth_s": t_synth,
     }
@@ -404,13 +477,18 @@ def main(argv=None):
         out["split_phase_form"] = {
             "frames_per_s": sp["fps"], "backprojection_ms": float(sp["stages"][:, 2].mean()),
             "p99_ms": 1e3 * float(np.percentile(sp["lat"], 99))}
+        progress("split-phase form done")
         out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
+        progress("paper configuration done")
         out["tab2_ablation"] = ablation(rc, synth, torch)
+        progress("Tab. II ablation done")
         sensors = make_sensors(rc, synth, torch, 32)
         out["batched_mixed"] = batched_mixed(rc, synth, torch, sensors)
+        progress(f"batched mixed: {out['batched_mixed']['frames_per_s']:.0f} frames/s")
         if args.serve_seconds > 0:
             out["serving"] = serving(rc, synth, torch, sensors, out["batched_mixed"]["frames_per_s"],
                                      args.serve_seconds)
+            progress("serving done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_budget)
     print(json.dumps(out), flush=True)
