@@ -28,27 +28,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "radar frames/s and p50/p99 frame latency at 1 MI355X; % HBM roofline"
 
-# gfx950 peak issue rate of FP32 VALU lane-instructions (non-packed): 256 CUs x
-# 128 lanes per clock x 2.4 GHz = 78.6e12/s, i.e. the published 157.3 TFLOP/s
-# FP32 vector peak with an FMA counted as two flops
+# gfx950 issue rates, in lanes per clock per CU (x 256 CUs x 2.4 GHz), as
+# measured with independent instruction streams on the GPU: FP32 add, multiply
+# and FMA 128 (78.6e12 lane-instructions/s, the published 157.3 TFLOP/s FP32
+# vector peak with an FMA counted as two flops); conversions, fractions and
+# integer shifts 64; transcendentals (sqrt, sin, cos) 32.  Costs below are in
+# issue slots of the fastest class.
 VALU_LANE_OPS = 256 * 128 * 2.4e9
-# sqrt, sin and cos issue at a quarter of that rate (measured: 18 vs 60 T/s)
+HALF_SLOTS = 2.0
 TRANS_SLOTS = 4.0
 HBM_PEAK_GBS = 8000.0
 
 
 def alg2_cost(chg: int):
-    """(algorithmic FP32 flops, VALU issue slots) per back-projection term.
+    """(algorithmic FP32 flops, issue slots) per back-projection term.
 
-    Flops (FMA = 2, sqrt/sin/cos = 1): d_rx 6, d_hyp 1, f_ind 2, index
-    fraction 1, phase product + reduction 2, sin + cos 2, interpolation 4
-    (table holds value and slope), complex multiply-accumulate 8 = 26, plus
-    the TX distance (6) once per group of chg channels sharing a TX position.
-    Slots: 17 full-rate VALU instructions + 3 transcendentals per term, plus
-    4 VALU + 1 transcendental per TX distance.
+    Flops (FMA = 2; sqrt, sin, cos, floor/fraction = 1): squared RX distance
+    and its square root 6, path sum 1, index 2, index fraction 1, sin + cos 2
+    (the hardware takes the phase in turns and reduces it), interpolation 4
+    (the table holds value and slope), complex multiply-accumulate 8 = 24 per
+    term, plus the TX distance with the pixel's correction term (7) once per
+    group of chg channels that share a TX position.
+    Slots: 11 add/mul/FMA (squared distance 3, path sum 1, index 1,
+    interpolation 2, multiply-accumulate 4), 3 half-rate (index conversion
+    and fraction, byte offset) and 3 transcendentals (sqrt, sin, cos) per
+    term, plus 4 add/FMA and 1 sqrt per TX distance.
     """
-    flops = 26.0 + 6.0 / chg
-    slots = 17.0 + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
+    flops = 24.0 + 7.0 / chg
+    slots = 11.0 + 3 * HALF_SLOTS + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
     return flops, slots
 
 
@@ -316,44 +323,49 @@ def mixed_plan_config(rc, synth, sensors, slots, **kw):
                          max_detections=1 << 14, **kw)
 
 
-def batched_mixed(rc, synth, torch, sensors, n_frames=256, slots=32):
-    """Frames of mixed sizes in batches of `slots` frames per rc_process_batch
-    (one back-projection launch per TX-group width and 16 frames); each batch
-    includes the pinned-memory upload of its beat cubes."""
+def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32):
+    """Frames of mixed sizes in batches of `batch` frames per rc_process_batch
+    (one back-projection launch per TX-group width and 16 frames), each batch
+    including the pinned-memory upload of its beat cubes.  Two batches are in
+    flight on two streams: the host prepares and enqueues the next batch while
+    the GPU processes the current one."""
     from paper_2306_09784_amd import serve
 
-    srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots), n_streams=1)
+    srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch), n_streams=2)
     try:
         order = [sensors[i % len(sensors)] for i in range(n_frames)]
         # warm-up batch
-        srv.submit([(10**6 + i, order[i], time.perf_counter()) for i in range(min(slots, n_frames))])
+        srv.submit([(10**6 + i, order[i], time.perf_counter()) for i in range(min(batch, n_frames))])
         srv.harvest(block=True)
         srv.results.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fid = 1
-        for b0 in range(0, n_frames, slots):
-            items = [(fid + i, order[b0 + i], time.perf_counter()) for i in range(min(slots, n_frames - b0))]
+        for b0 in range(0, n_frames, batch):
+            items = [(fid + i, order[b0 + i], time.perf_counter()) for i in range(min(batch, n_frames - b0))]
             fid += len(items)
             srv.submit(items)
-            srv.harvest(block=True)
+            srv.harvest_until(batch)
+        srv.harvest(block=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     finally:
         srv.close()
     terms = sum(s.frame.n_rows * s.frame.n_cols * s.frame.cfg.n_chirps * s.frame.cfg.n_channels for s in order)
-    return {"frames": n_frames, "batch": slots, "frames_per_s": n_frames / wall,
+    return {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "frames_per_s": n_frames / wall,
             "bp_terms_per_s_incl_all_stages": terms / wall, "wall_s": wall}
 
 
-def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=32):
+def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=64, max_batch=32):
     """Poisson arrivals from all sensors at `load` x the measured batch capacity,
-    continuous batching over the plan's slots, two streams."""
+    continuous batching over the plan's slots (at most max_batch frames per
+    batch, so a second batch can be admitted while one runs), two streams."""
     from paper_2306_09784_amd import serve
 
     srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots), n_streams=2)
     try:
-        res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s)
+        res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s,
+                                max_batch=max_batch)
     finally:
         srv.close()
     res["load"] = load

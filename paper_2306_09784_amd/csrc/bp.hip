@@ -10,11 +10,12 @@
 // the interpolation table by range compression.
 //
 // gfx950 mapping.  The loop is bound by VALU issue (three quarter-rate
-// transcendentals per term: sqrt, sin, cos, plus ~15 full-rate instructions),
-// so the design minimises instructions per term:
+// transcendentals per term: sqrt, sin, cos; three half-rate conversions and
+// shifts; eleven full-rate adds and FMAs), so the design minimises
+// instructions per term:
 //  * geometry is in aperture-local wavelength units, so a path length is its
-//    carrier phase in turns and needs only v_fract before the hardware
-//    sin/cos (which take turns);
+//    carrier phase in turns and goes straight into the hardware sin/cos
+//    (which take turns);
 //  * a squared distance is |P|^2 + |q|^2 - 2 P.q: two FMAs and an add with the
 //    per-row uniforms (-2 q, |q|^2), read with scalar loads;
 //  * channels sharing a TX position evaluate d_tx once per group;
@@ -126,15 +127,15 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       if constexpr (FORM == kBpSplit) {
         const float dlt = tx.d + rx.d;
         f = fmaf(a.a1, dlt, fb);
-        turn = __builtin_amdgcn_fractf(p.w + dlt);
+        turn = p.w + dlt;
       } else if constexpr (FORM == kBpExact) {
         const float d_hyp = tx.d + rx.d;
         f = fmaf(a.a1, d_hyp, tx.dop + rx.dop);
-        turn = __builtin_amdgcn_fractf(d_hyp);
+        turn = d_hyp;
       } else {
         const float d_hyp = tx.d + rx.d;
         f = fmaf(a.a1, d_hyp, fb);
-        turn = __builtin_amdgcn_fractf(d_hyp);
+        turn = d_hyp;
       }
       int i;
       if (CHECKED) {
@@ -155,6 +156,9 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   auto consume = [&](const Stage<U>& st, int par) {
 #pragma unroll
     for (int j = 0; j < U; ++j) {
+      // the hardware sin/cos take turns and reduce any argument exactly (checked
+      // to 2^16 turns: error 1.1e-7, as for arguments below one turn), so the
+      // path length in wavelengths goes in without a fraction
       const float sn = __builtin_amdgcn_sinf(st.turn[j]);  // sin(2 pi turn)
       const float cs = __builtin_amdgcn_cosf(st.turn[j]);
       const float vr = fmaf(st.phi[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
@@ -314,12 +318,13 @@ void bp_tiles(int n_rows, int n_cols, int* tiles_x, int* n_tiles) {
 }
 
 int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps) {
-  // 256 CUs x 4 SIMDs x 8 waves = 8192 resident waves; aim at two full
-  // generations of waves, at most 16 blocks and at least one chirp per block
+  // 256 CUs x 4 SIMDs x 8 waves = 8192 resident waves; aim at four
+  // generations of waves (the last, partial generation then idles a smaller
+  // share of the chip), at most 16 blocks and at least one chirp per block
   int tx, nt;
   bp_tiles((int)n_rows, (int)n_cols, &tx, &nt);
   const int64_t waves = (int64_t)nt * (kThreads / 64);
-  int64_t k = (16384 + waves - 1) / waves;
+  int64_t k = (4 * 8192 + waves - 1) / waves;
   if (k > 16) k = 16;
   if (k > n_chirps) k = n_chirps;
   return k < 1 ? 1 : (int)k;

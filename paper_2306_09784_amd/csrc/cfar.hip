@@ -23,14 +23,18 @@ constexpr int kMaxHalf = 16;  // guard + train <= 16
 constexpr int kHaloCols = kTileCols + 2 * kMaxHalf;
 constexpr int kHaloRows = kTileRows + 2 * kMaxHalf;
 
-__global__ __launch_bounds__(kThreads) void cfar_kernel(CfarArgs a) {
+__global__ __launch_bounds__(kThreads) void cfar_kernel(CfarMulti m) {
   __shared__ double pw[kHaloRows][kHaloCols];
   __shared__ double vo[kTileRows][kHaloCols];
   __shared__ double vi[kTileRows][kHaloCols];
+  const int fi = multi_frame(m, blockIdx.x);
+  const CfarArgs a = m.f[fi];
+  const int tile = blockIdx.x - m.begin[fi];
+  const int bx = tile % a.words_per_row, by = tile / a.words_per_row;  // one mask word per 64 columns
   const int h = a.guard + a.train;
   const int g = a.guard;
-  const int r0 = blockIdx.y * kTileRows;
-  const int c0 = blockIdx.x * kTileCols;
+  const int r0 = by * kTileRows;
+  const int c0 = bx * kTileCols;
   const int hr = kTileRows + 2 * h, hc = kTileCols + 2 * h;
 
   for (int e = threadIdx.x; e < hr * hc; e += kThreads) {
@@ -65,8 +69,8 @@ __global__ __launch_bounds__(kThreads) void cfar_kernel(CfarArgs a) {
   const bool tested = r >= h && r < a.n_rows - h && c >= h && c < a.n_cols - h;
   const bool det = tested && p > thr;
   const unsigned long long word = __ballot(det);
-  if (r < a.n_rows && lane == 0 && blockIdx.x < (unsigned)a.words_per_row)
-    a.mask[(int64_t)r * a.words_per_row + blockIdx.x] = word;
+  if (r < a.n_rows && lane == 0)
+    a.mask[(int64_t)r * a.words_per_row + bx] = word;
   const bool near = tested && fabs(p - thr) <= a.margin_rel * thr;
   bool listed = false;
   if (near && a.recheck_cap > 0) {
@@ -89,7 +93,8 @@ __global__ __launch_bounds__(kThreads) void cfar_kernel(CfarArgs a) {
 
 constexpr int kCompactThreads = 1024;
 
-__global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactArgs a) {
+__global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m) {
+  const CompactArgs a = m.f[__builtin_amdgcn_readfirstlane((int)blockIdx.x)];  // one workgroup per frame
   __shared__ int64_t scan[kCompactThreads];
   __shared__ int64_t base_sh;
   const int64_t n_words = (int64_t)a.n_rows * a.words_per_row;
@@ -131,20 +136,33 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactArgs a)
 
 }  // namespace
 
-hipError_t launch_cfar(const CfarArgs& a, hipStream_t s) {
-  if (a.n_rows <= 0 || a.n_cols <= 0) return hipSuccess;
-  if (a.guard < 0 || a.train < 1 || a.guard + a.train > kMaxHalf ||
-      a.words_per_row != (a.n_cols + kTileCols - 1) / kTileCols)
-    return hipErrorInvalidValue;
-  const dim3 grid((a.n_cols + kTileCols - 1) / kTileCols, (a.n_rows + kTileRows - 1) / kTileRows);
-  hipLaunchKernelGGL(cfar_kernel, grid, dim3(kThreads), 0, s, a);
+hipError_t launch_cfar(const CfarMulti& m0, hipStream_t s) {
+  if (m0.n_frames < 1 || m0.n_frames > CfarMulti::kMax) return hipErrorInvalidValue;
+  CfarMulti m = m0;
+  int64_t grid = 0;
+  for (int i = 0; i < m.n_frames; ++i) {
+    const CfarArgs& a = m.f[i];
+    if (a.n_rows < 0 || a.n_cols < 0 || a.guard < 0 || a.train < 1 || a.guard + a.train > kMaxHalf ||
+        a.words_per_row != (a.n_cols + kTileCols - 1) / kTileCols || (a.recheck_cap > 0 && (!a.listed || !a.n_listed)))
+      return hipErrorInvalidValue;
+    m.begin[i] = (int)grid;
+    grid += (int64_t)a.words_per_row * ((a.n_rows + kTileRows - 1) / kTileRows);
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  }
+  m.begin[m.n_frames] = (int)grid;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(cfar_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, m);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const CompactArgs& a, hipStream_t s) {
-  if (a.words_per_row != (a.n_cols + kTileCols - 1) / kTileCols || a.n_rows < 0 || a.cap < 0)
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kCompactThreads), 0, s, a);
+hipError_t launch_compact(const CompactMulti& m, hipStream_t s) {
+  if (m.n_frames < 1 || m.n_frames > CompactMulti::kMax) return hipErrorInvalidValue;
+  for (int i = 0; i < m.n_frames; ++i) {
+    const CompactArgs& a = m.f[i];
+    if (a.words_per_row != (a.n_cols + kTileCols - 1) / kTileCols || a.n_rows < 0 || a.cap < 0)
+      return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)m.n_frames), dim3(kCompactThreads), 0, s, m);
   return hipGetLastError();
 }
 

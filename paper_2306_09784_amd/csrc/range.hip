@@ -170,12 +170,14 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, float2* buf, int j,
 }
 
 template <int LOG2N>
-__global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeArgs a) {
+__global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeMulti m) {
   using F = Fft<LOG2N>;
   __shared__ float2 lds[F::RPW * F::PADN];
+  const int fi = multi_frame(m, blockIdx.x);
+  const RangeArgs a = m.f[fi];
   const int lrow = threadIdx.x / F::T;
   const int j = threadIdx.x - lrow * F::T;
-  const int64_t row = (int64_t)blockIdx.x * F::RPW + lrow;
+  const int64_t row = (int64_t)(blockIdx.x - m.begin[fi]) * F::RPW + lrow;
   const bool live = row < a.rows;
   float2* buf = lds + lrow * F::PADN;
   const float2* src = a.raw + (live ? row : 0) * a.n_s;
@@ -204,16 +206,24 @@ __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeArgs a) {
 }
 
 template <int LOG2N>
-hipError_t launch_fft(const RangeArgs& a, hipStream_t s) {
+hipError_t launch_fft(RangeMulti m, hipStream_t s) {
   using F = Fft<LOG2N>;
-  const int64_t grid = (a.rows + F::RPW - 1) / F::RPW;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(range_compress_kernel<LOG2N>, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+  int64_t grid = 0;
+  for (int i = 0; i < m.n_frames; ++i) {
+    m.begin[i] = (int)grid;
+    grid += (m.f[i].rows + F::RPW - 1) / F::RPW;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  }
+  m.begin[m.n_frames] = (int)grid;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(range_compress_kernel<LOG2N>, dim3((unsigned)grid), dim3(kThreads), 0, s, m);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kThreads) void spectrum_pairs_kernel(PairArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void spectrum_pairs_kernel(PairMulti m) {
+  const int fi = multi_frame(m, blockIdx.x);
+  const PairArgs a = m.f[fi];
+  const int64_t i = (int64_t)(blockIdx.x - m.begin[fi]) * kThreads + threadIdx.x;
   const int64_t total = a.rows * a.n_bins;
   if (i >= total) return;
   const int64_t row = i / a.n_bins;
@@ -226,34 +236,45 @@ __global__ __launch_bounds__(kThreads) void spectrum_pairs_kernel(PairArgs a) {
 
 }  // namespace
 
-hipError_t launch_range_compress(const RangeArgs& a, hipStream_t s) {
-  if (a.rows <= 0) return hipSuccess;
-  if (a.n_fft < 4 || (a.n_fft & (a.n_fft - 1)) || (1 << a.log2n) != a.n_fft || a.n_fft > 4096 ||
-      a.n_s < 1 || a.n_s > a.n_fft || a.n_bins < 1 || a.n_bins > a.n_fft || a.n_ch < 1 ||
-      a.tw_log2 < a.log2n || a.tw_log2 > 12)
-    return hipErrorInvalidValue;
-  switch (a.log2n) {
-    case 2: return launch_fft<2>(a, s);
-    case 3: return launch_fft<3>(a, s);
-    case 4: return launch_fft<4>(a, s);
-    case 5: return launch_fft<5>(a, s);
-    case 6: return launch_fft<6>(a, s);
-    case 7: return launch_fft<7>(a, s);
-    case 8: return launch_fft<8>(a, s);
-    case 9: return launch_fft<9>(a, s);
-    case 10: return launch_fft<10>(a, s);
-    case 11: return launch_fft<11>(a, s);
-    default: return launch_fft<12>(a, s);
+hipError_t launch_range_compress(const RangeMulti& m, hipStream_t s) {
+  if (m.n_frames < 1 || m.n_frames > RangeMulti::kMax) return hipErrorInvalidValue;
+  const int log2n = m.f[0].log2n;
+  for (int i = 0; i < m.n_frames; ++i) {
+    const RangeArgs& a = m.f[i];
+    if (a.rows < 0 || a.n_fft < 4 || (a.n_fft & (a.n_fft - 1)) || (1 << a.log2n) != a.n_fft ||
+        a.n_fft > 4096 || a.log2n != log2n || a.n_s < 1 || a.n_s > a.n_fft || a.n_bins < 1 ||
+        a.n_bins > a.n_fft || a.n_ch < 1 || a.tw_log2 < a.log2n || a.tw_log2 > 12)
+      return hipErrorInvalidValue;
+  }
+  switch (log2n) {
+    case 2: return launch_fft<2>(m, s);
+    case 3: return launch_fft<3>(m, s);
+    case 4: return launch_fft<4>(m, s);
+    case 5: return launch_fft<5>(m, s);
+    case 6: return launch_fft<6>(m, s);
+    case 7: return launch_fft<7>(m, s);
+    case 8: return launch_fft<8>(m, s);
+    case 9: return launch_fft<9>(m, s);
+    case 10: return launch_fft<10>(m, s);
+    case 11: return launch_fft<11>(m, s);
+    default: return launch_fft<12>(m, s);
   }
 }
 
-hipError_t launch_spectrum_pairs(const PairArgs& a, hipStream_t s) {
-  const int64_t total = a.rows * a.n_bins;
-  if (total <= 0) return hipSuccess;
-  if (a.n_ch < 1) return hipErrorInvalidValue;
-  const int64_t grid = (total + kThreads - 1) / kThreads;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(spectrum_pairs_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+hipError_t launch_spectrum_pairs(const PairMulti& m0, hipStream_t s) {
+  if (m0.n_frames < 1 || m0.n_frames > PairMulti::kMax) return hipErrorInvalidValue;
+  PairMulti m = m0;
+  int64_t grid = 0;
+  for (int i = 0; i < m.n_frames; ++i) {
+    const PairArgs& a = m.f[i];
+    if (a.n_ch < 1 || a.rows < 0 || a.n_bins < 1) return hipErrorInvalidValue;
+    m.begin[i] = (int)grid;
+    grid += (a.rows * a.n_bins + kThreads - 1) / kThreads;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  }
+  m.begin[m.n_frames] = (int)grid;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(spectrum_pairs_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, m);
   return hipGetLastError();
 }
 

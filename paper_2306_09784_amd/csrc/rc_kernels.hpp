@@ -12,6 +12,24 @@
 
 namespace rc {
 
+// Many frames in one launch: the launcher lays the workgroups of frame i out
+// as [begin[i], begin[i + 1]) and each workgroup finds its frame by a scan over
+// these (uniform) bounds, then reads that frame's arguments by value.
+template <class A, int MAXF>
+struct Multi {
+  static constexpr int kMax = MAXF;
+  int n_frames = 0;
+  int begin[MAXF + 1] = {};
+  A f[MAXF];
+};
+
+template <class M>
+__device__ __forceinline__ int multi_frame(const M& m, int w) {
+  int fi = 0;
+  while (fi + 1 < m.n_frames && w >= m.begin[fi + 1]) ++fi;
+  return __builtin_amdgcn_readfirstlane(fi);
+}
+
 // Range compression (beat signal -> beat spectrum): windowed, zero-padded
 // radix-2 decimation-in-time FFT per (chirp, channel) row in LDS, cropped to
 // n_bins.  Writes the interpolation table of back-projection: for bin k the
@@ -28,7 +46,9 @@ struct RangeArgs {
   int64_t rows;
   int n_s, n_fft, log2n, n_bins, n_ch;
 };
-hipError_t launch_range_compress(const RangeArgs& a, hipStream_t s);
+// every frame of one launch has the same n_fft
+using RangeMulti = Multi<RangeArgs, 32>;
+hipError_t launch_range_compress(const RangeMulti& m, hipStream_t s);
 
 // Caller-supplied spectrum -> interpolation table (same layout as above).
 struct PairArgs {
@@ -38,7 +58,8 @@ struct PairArgs {
   int64_t rows;
   int n_bins, n_ch;
 };
-hipError_t launch_spectrum_pairs(const PairArgs& a, hipStream_t s);
+using PairMulti = Multi<PairArgs, 32>;
+hipError_t launch_spectrum_pairs(const PairMulti& m, hipStream_t s);
 
 // Per-pixel tables, evaluated in double and rounded once:
 //  * f_doppler(p) in bins from the mean velocity at the aperture centre;
@@ -65,7 +86,8 @@ struct TableArgs {
   double a1;                      // bins per wavelength of path
   float* fbase;                   // [n_pix] (split only)
 };
-hipError_t launch_pixel_tables(const TableArgs& a, hipStream_t s);
+using TableMulti = Multi<TableArgs, 16>;
+hipError_t launch_pixel_tables(const TableMulti& m, hipStream_t s);
 
 // Back-projection (Alg. 2).  One lane per pixel; a wave covers an 8 x 8 block
 // of the lattice (or 1 x 64 for single-row lattices); channels that share a
@@ -158,7 +180,8 @@ struct CfarArgs {
   int* n_listed;
   int recheck_cap;
 };
-hipError_t launch_cfar(const CfarArgs& a, hipStream_t s);
+using CfarMulti = Multi<CfarArgs, 16>;
+hipError_t launch_cfar(const CfarMulti& m, hipStream_t s);
 
 // Double-precision recheck of the listed cells (see recheck.hip).
 struct RecheckArgs {
@@ -209,6 +232,7 @@ struct CompactArgs {
   int64_t cap;
   int64_t* count;
 };
-hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
+using CompactMulti = Multi<CompactArgs, 32>;
+hipError_t launch_compact(const CompactMulti& m, hipStream_t s);
 
 }  // namespace rc

@@ -131,11 +131,12 @@ int window_cells(const rc_plan_desc& d) {
 
 size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Pixel-blocks of partial images a slot may need: a frame is split into n_kb
-// chirp blocks only while it has fewer than 16384 waves (64 pixels each), so
-// n_kb * n_pix < 2^20 + n_pix; never more than 16 blocks.
+// Pixel-blocks of partial images a slot may need: a frame of W waves (64
+// lanes each, covering at least its n_pix pixels) is split into
+// n_kb = min(16, ceil(32768 / W)) chirp blocks, so
+// n_kb * n_pix <= min(16 n_pix, (32768 / W + 1) n_pix) <= min(16 n_pix, 2^21 + n_pix).
 int64_t partial_capacity(const rc_plan_desc& d) {
-  return std::min<int64_t>(16 * d.n_pix_max, (int64_t(1) << 20) + d.n_pix_max);
+  return std::min<int64_t>(16 * d.n_pix_max, (int64_t(1) << 21) + d.n_pix_max);
 }
 
 // staging/device geometry region: rowq[rows] and grpq[rows] float4; with the
@@ -291,10 +292,21 @@ int tx_group(const rc_frame& f) {
   return 1;
 }
 
-// Steps 1-2 of a frame (geometry upload, range compression, pixel tables) and
-// its back-projection descriptor; the batch launches back-projection for all
-// its frames at once (finish_frame then runs detection and the read-back).
-rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc::BpFrame* bf, int* chg_out) {
+// What a frame contributes to the batch-wide launches.
+struct Prepared {
+  bool raw_in = true;
+  rc::RangeArgs ra{};
+  rc::PairArgs pa{};
+  rc::TableArgs ta{};
+  rc::BpFrame bf{};
+  int chg = 1;
+};
+
+// Host part of a frame: geometry in local units through pinned staging (and,
+// with the recheck on, the double-precision spectrum), and the argument
+// blocks of its range compression, pixel tables and back-projection, which
+// the batch launches for many frames at once.
+rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Prepared* out) {
   const rc_plan_desc& d = p->d;
   const double c = d.radar.c > 0 ? d.radar.c : 299792458.0;
   const double mu = d.radar.bandwidth / d.radar.t_chirp;
@@ -377,9 +389,10 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   const bool timed = d.stage_timing != 0;
   if (timed) RC_HIP(hipEventRecord(s.stage_ev[0], st));
 
-  // 1. beat spectrum -> interpolation table
-  if (f.input_kind == RC_INPUT_RAW) {
-    rc::RangeArgs ra{};
+  // 1. beat spectrum -> interpolation table (launched batch-wide)
+  out->raw_in = f.input_kind == RC_INPUT_RAW;
+  if (out->raw_in) {
+    rc::RangeArgs& ra = out->ra;
     ra.raw = static_cast<const float2*>(f.data);
     ra.w_range = d_wrange;
     ra.w_sar = d_wsar;
@@ -393,10 +406,8 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
     ra.log2n = ilog2(f.n_fft);
     ra.n_bins = f.n_bins;
     ra.n_ch = f.n_channels;
-    RC_HIP(rc::launch_range_compress(ra, st));
   } else {
-    rc::PairArgs pa{static_cast<const float2*>(f.data), d_wsar, s.pairs, rows, f.n_bins, f.n_channels};
-    RC_HIP(rc::launch_spectrum_pairs(pa, st));
+    out->pa = rc::PairArgs{static_cast<const float2*>(f.data), d_wsar, s.pairs, rows, f.n_bins, f.n_channels};
   }
 
   if (recheck) {
@@ -418,11 +429,10 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
     r6.n_bins = f.n_bins;
     RC_HIP(rc::launch_range64(r6, st));
   }
-  if (timed) RC_HIP(hipEventRecord(s.stage_ev[1], st));
 
   // 2. per-frame tables: Doppler (Sec. III-D) and local pixel coordinates
   const float2* pix = reinterpret_cast<const float2*>(f.pixels);
-  rc::TableArgs ta{};
+  rc::TableArgs& ta = out->ta;
   ta.pix = pix;
   ta.n_pix = n_pix;
   ta.qt_x = st_x / rows; ta.qt_y = st_y / rows;
@@ -437,14 +447,11 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   ta.exact = exact;
   ta.a1 = a1 * lam;
   ta.fbase = s.fbase;
-  RC_HIP(rc::launch_pixel_tables(ta, st));
-  if (f.doppler_out)
-    RC_HIP(hipMemcpyAsync(f.doppler_out, s.fd, n_pix * sizeof(float), hipMemcpyDeviceToDevice, st));
 
   // back-projection descriptor (Alg. 2), launched batch-wide by the caller
   float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
   const int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps);
-  rc::BpFrame& ba = *bf;
+  rc::BpFrame& ba = out->bf;
   ba = rc::BpFrame{};
   ba.pixc = s.pixc;
   ba.fidx = d.precision == RC_PREC_FP32_SPLIT ? s.fbase : s.fd;
@@ -492,7 +499,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
     rk.qr_x = ta.qr_x; rk.qr_y = ta.qr_y;
     rk.v_x = vx; rk.v_y = vy;
   }
-  *chg_out = chg;
+  out->chg = chg;
   s.busy = true;
   s.frame_id = f.frame_id;
   s.n_rows = f.n_rows;
@@ -501,47 +508,65 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, rc:
   return RC_OK;
 }
 
-// Step 4 of a frame: CA-CFAR, ordered compaction and the asynchronous
-// read-back of the detections; records the frame's completion event.
-rc_status finish_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st) {
+// Step 4 of a batch: CA-CFAR of every frame, the double-precision recheck of
+// near-threshold cells (if on), ordered compaction, then per frame the
+// asynchronous read-back and its completion event.
+rc_status finish_batch(Plan* p, const std::vector<Slot*>& slot, const rc_frame* frames, int n, hipStream_t st) {
   const rc_plan_desc& d = p->d;
   const bool timed = d.stage_timing != 0;
-  float2* img = s.image_used;
-  // 4. CA-CFAR + ordered compaction, then the asynchronous read-back
   const int h = d.cfar_guard + d.cfar_train;
   const int n_train = (2 * h + 1) * (2 * h + 1) - (2 * d.cfar_guard + 1) * (2 * d.cfar_guard + 1);
   const double alpha = n_train * (std::pow(d.cfar_pfa, -1.0 / n_train) - 1.0);
-  const int wpr = (f.n_cols + 63) / 64;
   const bool recheck = d.max_rechecks > 0;
-  if (recheck) RC_HIP(rc::launch_clear_count(s.n_listed, st));
-  rc::CfarArgs ca{img, f.n_rows, f.n_cols, d.cfar_guard, d.cfar_train, alpha / n_train,
-                  d.cfar_margin_rel, s.mask, wpr, s.det_cell,
-                  s.listed, s.n_listed, recheck ? d.max_rechecks : 0};
-  RC_HIP(rc::launch_cfar(ca, st));
-  if (recheck) {
-    rc::RecheckArgs rk = s.rk;
-    rk.listed = s.listed;
-    rk.n_listed = s.n_listed;
-    rk.cap = d.max_rechecks;
-    rk.n_rows = f.n_rows;
-    rk.n_cols = f.n_cols;
-    rk.half = h;
-    rk.guard = d.cfar_guard;
-    rk.alpha_over_n = alpha / n_train;
-    rk.power = s.rpower;
-    rk.mask = s.mask;
-    rk.words_per_row = wpr;
-    rk.det_cell = s.det_cell;
-    RC_HIP(rc::launch_recheck(rk, st));
+  auto wpr = [&](int i) { return (frames[i].n_cols + 63) / 64; };
+  if (recheck)
+    for (int i = 0; i < n; ++i) RC_HIP(rc::launch_clear_count(slot[i]->n_listed, st));
+  for (int i0 = 0; i0 < n; i0 += rc::CfarMulti::kMax) {
+    rc::CfarMulti m;
+    for (int i = i0; i < n && m.n_frames < rc::CfarMulti::kMax; ++i) {
+      Slot& s = *slot[i];
+      m.f[m.n_frames++] = rc::CfarArgs{s.image_used, frames[i].n_rows, frames[i].n_cols, d.cfar_guard,
+                                       d.cfar_train, alpha / n_train, d.cfar_margin_rel, s.mask, wpr(i),
+                                       s.det_cell, s.listed, s.n_listed, recheck ? d.max_rechecks : 0};
+    }
+    RC_HIP(rc::launch_cfar(m, st));
   }
-  rc::CompactArgs pa{s.mask, s.det_cell, f.n_rows, f.n_cols, wpr, s.det_out,
-                     (int64_t)d.max_detections, s.det_count};
-  RC_HIP(rc::launch_compact(pa, st));
-  if (timed) RC_HIP(hipEventRecord(s.stage_ev[4], st));
-  RC_HIP(hipMemcpyAsync(s.h_count, s.det_count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  if (recheck) {
+    for (int i = 0; i < n; ++i) {
+      Slot& s = *slot[i];
+      rc::RecheckArgs rk = s.rk;
+      rk.listed = s.listed;
+      rk.n_listed = s.n_listed;
+      rk.cap = d.max_rechecks;
+      rk.n_rows = frames[i].n_rows;
+      rk.n_cols = frames[i].n_cols;
+      rk.half = h;
+      rk.guard = d.cfar_guard;
+      rk.alpha_over_n = alpha / n_train;
+      rk.power = s.rpower;
+      rk.mask = s.mask;
+      rk.words_per_row = wpr(i);
+      rk.det_cell = s.det_cell;
+      RC_HIP(rc::launch_recheck(rk, st));
+    }
+  }
+  for (int i0 = 0; i0 < n; i0 += rc::CompactMulti::kMax) {
+    rc::CompactMulti m;
+    for (int i = i0; i < n && m.n_frames < rc::CompactMulti::kMax; ++i) {
+      Slot& s = *slot[i];
+      m.f[m.n_frames++] = rc::CompactArgs{s.mask, s.det_cell, frames[i].n_rows, frames[i].n_cols, wpr(i),
+                                          s.det_out, (int64_t)d.max_detections, s.det_count};
+    }
+    RC_HIP(rc::launch_compact(m, st));
+  }
   const int prefix = std::min(kDetPrefix, d.max_detections);
-  RC_HIP(hipMemcpyAsync(s.h_det, s.det_out, prefix * sizeof(rc_detection), hipMemcpyDeviceToHost, st));
-  RC_HIP(hipEventRecord(s.done, st));
+  for (int i = 0; i < n; ++i) {
+    Slot& s = *slot[i];
+    if (timed) RC_HIP(hipEventRecord(s.stage_ev[4], st));
+    RC_HIP(hipMemcpyAsync(s.h_count, s.det_count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    RC_HIP(hipMemcpyAsync(s.h_det, s.det_out, prefix * sizeof(rc_detection), hipMemcpyDeviceToHost, st));
+    RC_HIP(hipEventRecord(s.done, st));
+  }
   return RC_OK;
 }
 
@@ -672,31 +697,73 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<Slot*> slot(n_frames, nullptr);
-  std::vector<rc::BpFrame> bpf(n_frames);
-  std::vector<int> chg(n_frames, 1);
+  std::vector<Prepared> prep(n_frames);
   auto undo = [&](rc_status r) {  // a failed batch leaves no slot busy
     (void)hipStreamSynchronize(st);
     for (Slot* q : slot)
       if (q) { q->busy = false; q->frame_id = -1; }
     return r;
   };
-  // 1-2: per-frame geometry, range compression and pixel tables
+#define RC_BATCH(call)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return undo(fail(RC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)));        \
+  } while (0)
+  const bool timed = p->d.stage_timing != 0;
+  // host part of every frame: geometry upload, argument blocks
   for (int i = 0; i < n_frames; ++i) {
     for (Slot& c : p->slots)
       if (!c.busy) { slot[i] = &c; break; }
-    rc_status r = prepare_frame(p, *slot[i], frames[i], st, &bpf[i], &chg[i]);
+    rc_status r = prepare_frame(p, *slot[i], frames[i], st, &prep[i]);
     if (r != RC_OK) return undo(r);
   }
-  const bool timed = p->d.stage_timing != 0;
+  // 1: range compression, one launch per DFT length and 32 frames
+  {
+    std::vector<char> done(n_frames, 0);
+    for (int i = 0; i < n_frames; ++i) {
+      if (done[i] || !prep[i].raw_in) continue;
+      rc::RangeMulti m;
+      for (int j = i; j < n_frames && m.n_frames < rc::RangeMulti::kMax; ++j)
+        if (!done[j] && prep[j].raw_in && prep[j].ra.log2n == prep[i].ra.log2n) {
+          m.f[m.n_frames++] = prep[j].ra;
+          done[j] = 1;
+        }
+      RC_BATCH(rc::launch_range_compress(m, st));
+    }
+    rc::PairMulti m;
+    for (int i = 0; i < n_frames; ++i) {
+      if (prep[i].raw_in) continue;
+      m.f[m.n_frames++] = prep[i].pa;
+      if (m.n_frames == rc::PairMulti::kMax) {
+        RC_BATCH(rc::launch_spectrum_pairs(m, st));
+        m.n_frames = 0;
+      }
+    }
+    if (m.n_frames) RC_BATCH(rc::launch_spectrum_pairs(m, st));
+  }
   if (timed)
-    for (Slot* q : slot) RC_HIP(hipEventRecord(q->stage_ev[2], st));
+    for (Slot* q : slot) RC_BATCH(hipEventRecord(q->stage_ev[1], st));
+  // 2: pixel tables, one launch per 16 frames
+  for (int i0 = 0; i0 < n_frames; i0 += rc::TableMulti::kMax) {
+    rc::TableMulti m;
+    for (int i = i0; i < n_frames && m.n_frames < rc::TableMulti::kMax; ++i) m.f[m.n_frames++] = prep[i].ta;
+    RC_BATCH(rc::launch_pixel_tables(m, st));
+  }
+  for (int i = 0; i < n_frames; ++i)
+    if (frames[i].doppler_out)
+      RC_BATCH(hipMemcpyAsync(frames[i].doppler_out, slot[i]->fd,
+                              (size_t)frames[i].n_rows * frames[i].n_cols * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (timed)
+    for (Slot* q : slot) RC_BATCH(hipEventRecord(q->stage_ev[2], st));
   // 3: back-projection, one launch per TX-group width and per 16 frames; the
   // frames of a launch go most expensive work item first (fewest short items
   // in the tail)
   std::vector<int> order(n_frames);
   for (int i = 0; i < n_frames; ++i) order[i] = i;
   auto item_cost = [&](int i) {
-    return (int64_t)((bpf[i].n_chirps + bpf[i].n_kb - 1) / bpf[i].n_kb) * bpf[i].n_ch;
+    const rc::BpFrame& b = prep[i].bf;
+    return (int64_t)((b.n_chirps + b.n_kb - 1) / b.n_kb) * b.n_ch;
   };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return item_cost(x) > item_cost(y); });
   std::vector<char> done(n_frames, 0);
@@ -704,40 +771,38 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     const int i = order[oi];
     if (done[i]) continue;
     rc::BpBatch b{};
-    b.chg = chg[i];
+    b.chg = prep[i].chg;
     b.form = p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
              : p->d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
     for (int oj = oi; oj < n_frames && b.n_frames < rc::kBpMaxFrames; ++oj) {
       const int j = order[oj];
-      if (done[j] || chg[j] != chg[i]) continue;
-      rc::BpFrame fj = bpf[j];
+      if (done[j] || prep[j].chg != prep[i].chg) continue;
+      rc::BpFrame fj = prep[j].bf;
       fj.chunk = (fj.n_kb * fj.n_tiles + 7) / 8;
       fj.slot_base = b.n_slots;
       b.f[b.n_frames++] = fj;
       b.n_slots += fj.chunk;
       done[j] = 1;
     }
-    hipError_t e = rc::launch_backproject(b, st);
-    if (e != hipSuccess) return undo(fail(RC_EHIP, "back-projection launch: %s", hipGetErrorString(e)));
+    RC_BATCH(rc::launch_backproject(b, st));
   }
   rc::ReduceBatch rb{};
   for (int i = 0; i < n_frames; ++i) {
-    if (bpf[i].n_kb == 1) continue;
-    rb.f[rb.n_frames++] = rc::ReduceFrame{bpf[i].out, slot[i]->image_used,
-                                          (int64_t)frames[i].n_rows * frames[i].n_cols, bpf[i].n_kb};
+    if (prep[i].bf.n_kb == 1) continue;
+    rb.f[rb.n_frames++] = rc::ReduceFrame{prep[i].bf.out, slot[i]->image_used,
+                                          (int64_t)frames[i].n_rows * frames[i].n_cols, prep[i].bf.n_kb};
     if (rb.n_frames == rc::kReduceMaxFrames) {
-      RC_HIP(rc::launch_reduce_partials(rb, st));
+      RC_BATCH(rc::launch_reduce_partials(rb, st));
       rb.n_frames = 0;
     }
   }
-  if (rb.n_frames) RC_HIP(rc::launch_reduce_partials(rb, st));
+  if (rb.n_frames) RC_BATCH(rc::launch_reduce_partials(rb, st));
   if (timed)
-    for (Slot* q : slot) RC_HIP(hipEventRecord(q->stage_ev[3], st));
-  // 4: detection and read-back per frame
-  for (int i = 0; i < n_frames; ++i) {
-    rc_status r = finish_frame(p, *slot[i], frames[i], st);
-    if (r != RC_OK) return r;
-  }
+    for (Slot* q : slot) RC_BATCH(hipEventRecord(q->stage_ev[3], st));
+#undef RC_BATCH
+  // 4: detection and read-back
+  rc_status r = finish_batch(p, slot, frames, n_frames, st);
+  if (r != RC_OK) return undo(r);
   return RC_OK;
 }
 

@@ -35,8 +35,10 @@ __device__ __forceinline__ double radial(double px, double py, double qx, double
   return d > 0.0 ? (rx * vx + ry * vy) / d : 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableMulti m) {
+  const int fi = multi_frame(m, blockIdx.x);
+  const TableArgs a = m.f[fi];
+  const int64_t i = (int64_t)(blockIdx.x - m.begin[fi]) * kThreads + threadIdx.x;
   if (i >= a.n_pix) return;
   const float2 p = a.pix[i];
   const double px = p.x, py = p.y;
@@ -63,11 +65,19 @@ __global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableArgs a) {
 
 }  // namespace
 
-hipError_t launch_pixel_tables(const TableArgs& a, hipStream_t s) {
-  if (a.n_pix <= 0) return hipSuccess;
-  const int64_t grid = (a.n_pix + kThreads - 1) / kThreads;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pixel_tables_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
+hipError_t launch_pixel_tables(const TableMulti& m0, hipStream_t s) {
+  if (m0.n_frames < 1 || m0.n_frames > TableMulti::kMax) return hipErrorInvalidValue;
+  TableMulti m = m0;
+  int64_t grid = 0;
+  for (int i = 0; i < m.n_frames; ++i) {
+    if (m.f[i].n_pix < 0) return hipErrorInvalidValue;
+    m.begin[i] = (int)grid;
+    grid += (m.f[i].n_pix + kThreads - 1) / kThreads;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  }
+  m.begin[m.n_frames] = (int)grid;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(pixel_tables_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, m);
   return hipGetLastError();
 }
 

@@ -99,21 +99,32 @@ class Server:
                 self.inflight[fid] = (slot, sens.sensor_id, arrival, now)
         self.plan.process(descs, stream)
 
+    def _complete(self, fid: int) -> None:
+        slot, sid, arrival, admitted = self.inflight.pop(fid)
+        dets = self.plan.detections(fid)
+        done = time.perf_counter()
+        if self.images is not None:
+            self.torch.cuda.synchronize()
+            self.image_of[fid] = self.images[slot].cpu().numpy().copy()
+        self.plan.release(fid)
+        self.free.append(slot)
+        self.results.append(Completed(fid, sid, arrival, admitted, done, dets))
+
     def harvest(self, block: bool = False) -> int:
-        """Collects every completed frame; returns how many completed."""
+        """Collects every completed frame (all in flight if block); returns how many."""
         n = 0
         for fid in list(self.inflight):
             if not block and not self.plan.poll(fid):
                 continue
-            slot, sid, arrival, admitted = self.inflight.pop(fid)
-            dets = self.plan.detections(fid)
-            done = time.perf_counter()
-            if self.images is not None:
-                self.torch.cuda.synchronize()
-                self.image_of[fid] = self.images[slot].cpu().numpy().copy()
-            self.plan.release(fid)
-            self.free.append(slot)
-            self.results.append(Completed(fid, sid, arrival, admitted, done, dets))
+            self._complete(fid)
+            n += 1
+        return n
+
+    def harvest_until(self, max_inflight: int) -> int:
+        """Waits for the oldest frames in flight until at most max_inflight remain."""
+        n = 0
+        while len(self.inflight) > max_inflight:
+            self._complete(next(iter(self.inflight)))
             n += 1
         return n
 
