@@ -16,6 +16,8 @@ x 16 virtual channels (4 TX x 4 RX), complex64; 64 point targets, SNR uniform
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -199,17 +201,18 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
             step(i)
             plan.release(i)
         torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for i in range(steps):
-            fid = 1000 + i
-            t0 = time.perf_counter()
-            dets = step(fid)
-            lat.append(time.perf_counter() - t0)
-            stages.append(plan.stage_times(fid))
-            plan.release(fid)
-            n_det = len(dets)
-        torch.cuda.synchronize()
-        total = time.perf_counter() - t_start
+        with no_gc():
+            t_start = time.perf_counter()
+            for i in range(steps):
+                fid = 1000 + i
+                t0 = time.perf_counter()
+                dets = step(fid)
+                lat.append(time.perf_counter() - t0)
+                stages.append(plan.stage_times(fid))
+                plan.release(fid)
+                n_det = len(dets)
+            torch.cuda.synchronize()
+            total = time.perf_counter() - t_start
     res = {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
     if want_image:
         res["image"] = img.cpu().numpy().view(np.complex64).reshape(-1)
@@ -227,10 +230,27 @@ def paper_config(rc, synth, torch, steps):
     pix = rc.grid_polar(g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"])
     x0, x1, y0, y1 = cfg.box
     in_box = int(np.sum((pix[:, 0] >= x0) & (pix[:, 0] <= x1) & (pix[:, 1] >= y0) & (pix[:, 1] <= y1)))
-    run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, steps, 1)
+    run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, steps, 1,
+                        want_image=True)
     n_pix = g["nth"] * g["nr"]
     terms = float(n_pix) * cfg.n_chirps * cfg.n_channels
     bp_ms = float(run["stages"][:, 2].mean())
+    # Fig. 3's comparison: the polar image shown on the 2.5 cm Cartesian grid
+    # (rc_resample_polar) against the image formed on that grid directly
+    cart = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_PREC_FP32, 1, 1,
+                         want_image=True)
+    dev = torch.device("cuda")
+    d_img = torch.from_numpy(run["image"]).to(dev)
+    d_pts = torch.from_numpy(np.ascontiguousarray(frame.pix)).to(dev)
+    shown = torch.empty(frame.pix.shape[0], dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rc.resample_polar(d_img, g, d_pts, shown, stream)  # warm-up
+    e0.record(stream)
+    rc.resample_polar(d_img, g, d_pts, shown, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    shown_h = shown.cpu().numpy()
     return {
         "workload": (f"paper-polar: {cfg.n_samples} samples x {cfg.n_chirps} chirps x {cfg.n_channels} RX, polar "
                      f"lattice {g['nth']} x {g['nr']} (dr {g['dr'] * 100:.2f} cm, dth {g['dth'] * 1e3:.2f} mrad, "
@@ -240,6 +260,12 @@ def paper_config(rc, synth, torch, steps):
         "backprojection_ms": bp_ms,
         "bp_terms_per_s": terms / (bp_ms * 1e-3),
         "p99_ms": 1e3 * float(np.percentile(run["lat"], 99)),
+        "polar_on_cartesian": {
+            "resample_ms": e0.elapsed_time(e1),
+            "target_gain_db_vs_cartesian_image": _target_gain_db(shown_h, frame.pix, frame.targets,
+                                                                 cart["image"], frame.pix),
+            "cartesian_bp_ms": float(cart["stages"][:, 2].mean()),
+        },
         "paper_tab2_row8": {"gpu": "GTX 1080 Ti (FP32, pyCUDA)", "bp_ms": 15.5, "total_ms": 18.8,
                             "bp_terms": 165061 * 1024 * 8, "bp_terms_per_s": 165061 * 1024 * 8 / 15.5e-3},
     }
@@ -339,16 +365,17 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32):
         srv.harvest(block=True)
         srv.results.clear()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fid = 1
-        for b0 in range(0, n_frames, batch):
-            items = [(fid + i, order[b0 + i], time.perf_counter()) for i in range(min(batch, n_frames - b0))]
-            fid += len(items)
-            srv.submit(items)
-            srv.harvest_until(batch)
-        srv.harvest(block=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with no_gc():
+            t0 = time.perf_counter()
+            fid = 1
+            for b0 in range(0, n_frames, batch):
+                items = [(fid + i, order[b0 + i], time.perf_counter()) for i in range(min(batch, n_frames - b0))]
+                fid += len(items)
+                srv.submit(items)
+                srv.harvest_until(batch)
+            srv.harvest(block=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
     finally:
         srv.close()
     terms = sum(s.frame.n_rows * s.frame.n_cols * s.frame.cfg.n_chirps * s.frame.cfg.n_channels for s in order)
@@ -364,13 +391,25 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
 
     srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots), n_streams=2)
     try:
-        res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s,
-                                max_batch=max_batch)
+        with no_gc():
+            res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s,
+                                    max_batch=max_batch)
     finally:
         srv.close()
     res["load"] = load
     res["realtime_bound_ms"] = 1024 * synth.RADAR["t_pri"] * 1e3
     return res
+
+
+@contextlib.contextmanager
+def no_gc():
+    """Python's cyclic collector paused during a timed host loop (collected before)."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def progress(msg: str) -> None:

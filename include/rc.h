@@ -236,6 +236,25 @@ rc_status rc_grid_polar_params(const rc_radar* radar, double x0, double x1, doub
 rc_status rc_grid_polar(double ox, double oy, double r0, double dr, int32_t nr,
                         double th0, double dth, int32_t nth, float* xy);
 
+/* Magnitude of a polar-grid image at arbitrary points (Sec. III-E: the image
+ * is formed on the polar lattice; showing it on the Cartesian reference grid,
+ * as the comparison of Fig. 3 does, needs its magnitude at Cartesian points).
+ *   polar_image  device, complex64 [nth][nr] (the layout rc_grid_polar gives
+ *                the pixels: theta slow), e.g. a frame's image_out;
+ *   ox, oy, r0, dr, th0, dth  the lattice (as from rc_grid_polar_params);
+ *   points       device, float [n_points][2], metres;
+ *   out          device, float [n_points].
+ * For a point at range r and azimuth theta (from +y towards +x) around
+ * (ox, oy), u = (r - r0) / dr and v = (theta - th0) / dth index the lattice;
+ * |P| is interpolated bilinearly in (v, u), an index equal to the last one
+ * takes that sample, and a point outside [0, nth - 1] x [0, nr - 1] gets 0.
+ * Enqueued on `stream` (hipStream_t, NULL = default); the caller keeps the
+ * buffers alive until it completes.  RC_EINVAL for null buffers, nth or
+ * nr < 1, dr or dth not positive and finite, or n_points < 0. */
+rc_status rc_resample_polar(const void* polar_image, int32_t nth, int32_t nr, double ox, double oy,
+                            double r0, double dr, double th0, double dth, const void* points,
+                            int64_t n_points, void* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

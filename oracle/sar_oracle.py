@@ -53,6 +53,7 @@ __all__ = [
     "cartesian_grid",
     "polar_grid_params",
     "polar_grid",
+    "resample_polar",
     "cfar_alpha",
     "ca_cfar",
     "to_db",
@@ -360,6 +361,37 @@ def polar_grid(ox: float, oy: float, r0: float, dr: float, nr: int,
     out[:, :, 0] = ox + r[None, :] * np.sin(th)[:, None]
     out[:, :, 1] = oy + r[None, :] * np.cos(th)[:, None]
     return out.reshape(-1, 2)
+
+
+def resample_polar(img_polar: np.ndarray, ox: float, oy: float, r0: float, dr: float, nr: int,
+                   th0: float, dth: float, nth: int, points: np.ndarray) -> np.ndarray:
+    """Magnitude of a polar-grid image at arbitrary points (metres).
+
+    Sec. III-E forms the image on a polar lattice; showing it on the
+    Cartesian reference grid (the comparison of Fig. 3) needs the magnitude
+    at Cartesian points.  A point's range r and azimuth theta (from +y
+    towards +x, as in ``polar_grid``) give fractional lattice indices
+    u = (r - r0) / dr, v = (theta - th0) / dth; |P| is interpolated
+    bilinearly in (v, u) with the rule of ``interp_index`` on each axis (an
+    index equal to the last one takes that sample; outside [0, n - 1] the
+    result is 0).  The magnitude, not the complex value, is interpolated: the
+    image's phase turns over once per half wavelength of range, far faster
+    than the lattice samples it.
+    """
+    A = np.abs(np.asarray(img_polar)).astype(np.float64).reshape(nth, nr)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 2)
+    dx, dy = pts[:, 0] - ox, pts[:, 1] - oy
+    u = (np.hypot(dx, dy) - r0) / dr
+    v = (np.arctan2(dx, dy) - th0) / dth
+    valid = (u >= 0) & (u <= nr - 1) & (v >= 0) & (v <= nth - 1)
+    us, vs = np.where(valid, u, 0.0), np.where(valid, v, 0.0)
+    iu = np.minimum(np.floor(us).astype(np.int64), nr - 1)
+    iv = np.minimum(np.floor(vs).astype(np.int64), nth - 1)
+    fu, fv = us - iu, vs - iv
+    iu1, iv1 = np.minimum(iu + 1, nr - 1), np.minimum(iv + 1, nth - 1)
+    out = ((1 - fv) * ((1 - fu) * A[iv, iu] + fu * A[iv, iu1]) +
+           fv * ((1 - fu) * A[iv1, iu] + fu * A[iv1, iu1]))
+    return np.where(valid, out, 0.0)
 
 
 # ---------------------------------------------------------------------------

@@ -235,4 +235,16 @@ struct CompactArgs {
 using CompactMulti = Multi<CompactArgs, 32>;
 hipError_t launch_compact(const CompactMulti& m, hipStream_t s);
 
+// Magnitude of a polar-grid image [nth][nr] at n points (metres), bilinear
+// in (theta, r); zero outside the lattice.
+struct ResampleArgs {
+  const float2* img;
+  int nth, nr;
+  double ox, oy, r0, dr, th0, dth;
+  const float2* pts;
+  int64_t n;
+  float* out;
+};
+hipError_t launch_resample_polar(const ResampleArgs& a, hipStream_t s);
+
 }  // namespace rc

@@ -940,4 +940,20 @@ rc_status rc_grid_polar(double ox, double oy, double r0, double dr, int32_t nr, 
   return RC_OK;
 }
 
+rc_status rc_resample_polar(const void* polar_image, int32_t nth, int32_t nr, double ox, double oy,
+                            double r0, double dr, double th0, double dth, const void* points,
+                            int64_t n_points, void* out, void* stream) {
+  if (n_points < 0) return fail(RC_EINVAL, "n_points must be >= 0");
+  if (n_points == 0) return RC_OK;
+  if (!polar_image || !points || !out) return fail(RC_EINVAL, "image, points and out are required");
+  if (nth < 1 || nr < 1) return fail(RC_EINVAL, "need nth >= 1 and nr >= 1");
+  if (!(dr > 0) || !(dth > 0) || !std::isfinite(dr) || !std::isfinite(dth) || !std::isfinite(r0) ||
+      !std::isfinite(th0) || !std::isfinite(ox) || !std::isfinite(oy))
+    return fail(RC_EINVAL, "lattice parameters must be finite with dr, dth > 0");
+  rc::ResampleArgs a{static_cast<const float2*>(polar_image), nth, nr, ox, oy, r0, dr, th0, dth,
+                     static_cast<const float2*>(points), n_points, static_cast<float*>(out)};
+  RC_HIP(rc::launch_resample_polar(a, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
 }  // extern "C"

@@ -104,7 +104,7 @@ DETECTION_DTYPE = np.dtype([("pixel", "<i4"), ("power", "<f4"), ("threshold", "<
 ENTRY_POINTS = [
     "rc_plan_create", "rc_plan_slot_bytes", "rc_process_batch", "rc_poll", "rc_detections",
     "rc_image", "rc_stage_times", "rc_frame_release", "rc_plan_destroy", "rc_last_error", "rc_grid_cartesian",
-    "rc_grid_polar_params", "rc_grid_polar",
+    "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar",
 ]
 
 
@@ -142,6 +142,8 @@ def _load():
                                            C.c_double, dp]),
         "rc_grid_polar": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, i32, C.c_double,
                                     C.c_double, i32, vp]),
+        "rc_resample_polar": (C.c_int, [vp, i32, i32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -184,6 +186,15 @@ def grid_polar(ox, oy, r0, dr, nr, th0, dth, nth) -> np.ndarray:
     out = np.empty((nth * nr, 2), dtype=np.float32)
     check(lib.rc_grid_polar(ox, oy, r0, dr, nr, th0, dth, nth, out.ctypes.data), "rc_grid_polar")
     return out
+
+
+def resample_polar(polar_image, g: dict, points, out, stream=None) -> None:
+    """rc_resample_polar: |image| on the polar lattice `g` (grid_polar_params
+    keys) at device `points` (float32 [n, 2]) into device `out` (float32 [n])."""
+    n = int(out.numel()) if hasattr(out, "numel") else int(np.asarray(out).size)
+    check(lib.rc_resample_polar(_ptr(polar_image), int(g["nth"]), int(g["nr"]), float(g["ox"]), float(g["oy"]),
+                                float(g["r0"]), float(g["dr"]), float(g["th0"]), float(g["dth"]), _ptr(points),
+                                n, _ptr(out), _stream_handle(stream)), "rc_resample_polar")
 
 
 # ---------------------------------------------------------------------------

@@ -400,6 +400,48 @@ def test_polar_grid_steps_and_coverage():
     assert g["th0"] <= math.atan2(-15, 1) + 1e-12 and g["th0"] + g["nth"] * g["dth"] >= math.atan2(15, 1)
 
 
+def _polar_fixture():
+    g = dict(ox=0.3, oy=-0.2, r0=2.0, dr=0.05, nr=40, th0=-0.6, dth=0.02, nth=50)
+    r = g["r0"] + g["dr"] * np.arange(g["nr"])
+    th = g["th0"] + g["dth"] * np.arange(g["nth"])
+    return g, r, th
+
+
+def test_resample_polar_reproduces_bilinear_functions():
+    """Bilinear interpolation in (theta, r) is exact for a + b r + c theta + d r theta."""
+    g, r, th = _polar_fixture()
+    a, b, c, d = 5.0, 0.7, 1.3, 0.4
+    f = lambda rr, tt: a + b * rr + c * tt + d * rr * tt  # noqa: E731  (positive on the lattice)
+    img = (f(r[None, :], th[:, None]) * np.exp(1j * 2.1)).astype(np.complex128)  # phase must not matter
+    rng = np.random.default_rng(5)
+    rr = rng.uniform(r[0], r[-1], 500)
+    tt = rng.uniform(th[0], th[-1], 500)
+    pts = np.stack([g["ox"] + rr * np.sin(tt), g["oy"] + rr * np.cos(tt)], axis=1)
+    out = O.resample_polar(img, g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"], pts)
+    np.testing.assert_allclose(out, f(rr, tt), rtol=1e-12)
+
+
+def test_resample_polar_nodes_edges_and_outside():
+    g, r, th = _polar_fixture()
+    rng = np.random.default_rng(6)
+    img = rng.standard_normal((g["nth"], g["nr"])) + 1j * rng.standard_normal((g["nth"], g["nr"]))
+    # lattice nodes, including the last row and column, return the node magnitude
+    iv = np.array([0, 7, g["nth"] - 1, g["nth"] - 1, 0])
+    iu = np.array([0, 13, g["nr"] - 1, 0, g["nr"] - 1])
+    pts = np.stack([g["ox"] + r[iu] * np.sin(th[iv]), g["oy"] + r[iu] * np.cos(th[iv])], axis=1)
+    out = O.resample_polar(img, g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"], pts)
+    np.testing.assert_allclose(out, np.abs(img[iv, iu]), rtol=1e-9)
+    # halfway between two range samples: their mean magnitude
+    pm = np.array([[g["ox"] + (r[3] + r[4]) / 2 * np.sin(th[9]), g["oy"] + (r[3] + r[4]) / 2 * np.cos(th[9])]])
+    mid = O.resample_polar(img, g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"], pm)
+    assert mid[0] == pytest.approx((abs(img[9, 3]) + abs(img[9, 4])) / 2, rel=1e-9)
+    # beyond the last range, before the first angle, at the origin: zero
+    far = np.array([[g["ox"], g["oy"] + r[-1] + 0.01], [g["ox"] + 3.0 * np.sin(th[0] - 0.01), g["oy"] + 3.0 * np.cos(th[0] - 0.01)],
+                    [g["ox"], g["oy"]]])
+    out = O.resample_polar(img, g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"], far)
+    assert np.all(out == 0.0)
+
+
 def test_cartesian_grid_layout():
     p = O.cartesian_grid(-1.0, 0.5, 5, 2.0, 0.25, 3)
     assert p.shape == (15, 2)
