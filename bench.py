@@ -193,7 +193,7 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
         def step(fid):
             fr = rc.Plan.make_frame(fid, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
                                     n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins, n_fft=frame.n_fft,
-                                    fs=frame.fs, n_samples=cfg.n_samples, image_out=img)
+                                    fs=frame.fs, n_samples=cfg.n_samples, image_out=img, height=cfg.height)
             plan.process([fr], stream)
             return plan.detections(fid)
 

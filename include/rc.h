@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define RC_ABI_VERSION 1
+#define RC_ABI_VERSION 2
 
 typedef enum rc_status {
   RC_OK = 0,
@@ -145,6 +145,9 @@ typedef struct rc_frame {
   float* doppler_out;           /* device float [n_rows * n_cols] (bins) or NULL  */
   void* spectrum_out;           /* device complex64 [n_chirps][n_channels][n_bins]
                                    beat spectrum before w_sar, or NULL            */
+  double height;                /* antennas above the plane of the pixels, metres:
+                                   distances become sqrt(|p - q|^2 + height^2);
+                                   0 is the paper's planar geometry               */
 } rc_frame;
 
 #define RC_DET_NEAR_THRESHOLD 1u  /* in the band, decided in single precision */

@@ -167,14 +167,16 @@ def interp_index(row: np.ndarray, f: np.ndarray) -> np.ndarray:
 # Doppler table (Sec. III-D; the f_doppler term of Alg. 2's index)
 # ---------------------------------------------------------------------------
 def doppler_table(pix: np.ndarray, q_tx: np.ndarray, q_rx: np.ndarray,
-                  vel: np.ndarray, kd: float) -> np.ndarray:
+                  vel: np.ndarray, kd: float, height: float = 0.0) -> np.ndarray:
     """Per-pixel Doppler shift in bins from the average velocity.
 
     Sec. III-D: the velocity is taken as constant over the chirp sequence, so
     the radial velocity components of Alg. 1 are evaluated once per
     pixel with the mean velocity, at the aperture centre (mean TX and mean RX
     position over every chirp and channel).  A pixel that coincides with a
-    reference position gets a zero radial term.
+    reference position gets a zero radial term.  With the radar ``height``
+    above the pixels' plane the distance is 3-D and the (horizontal) velocity
+    projects on the 3-D line of sight.
     """
     pix = np.asarray(pix, dtype=np.float64).reshape(-1, 2)
     qt = np.asarray(q_tx, dtype=np.float64).reshape(-1, 2).mean(axis=0)
@@ -183,7 +185,7 @@ def doppler_table(pix: np.ndarray, q_tx: np.ndarray, q_rx: np.ndarray,
 
     def radial(q):
         r = pix - q
-        d = np.sqrt(np.sum(r * r, axis=1))
+        d = np.sqrt(np.sum(r * r, axis=1) + height * height)
         num = r @ v
         out = np.zeros_like(d)
         nz = d > 0
@@ -196,11 +198,13 @@ def doppler_table(pix: np.ndarray, q_tx: np.ndarray, q_rx: np.ndarray,
 # ---------------------------------------------------------------------------
 # Alg. 2: optimised back-projection
 # ---------------------------------------------------------------------------
-def _norm2(a: np.ndarray) -> np.ndarray:
-    return np.sqrt(np.sum(a * a, axis=-1))
+def _norm2(a: np.ndarray, height: float = 0.0) -> np.ndarray:
+    """Distance for in-plane differences a [..., 2] with the radar `height`
+    above the plane (the paper's planar geometry is height 0)."""
+    return np.sqrt(np.sum(a * a, axis=-1) + height * height)
 
 
-def bp_alg2(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, a2, chunk: int = 4096):
+def bp_alg2(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, a2, chunk: int = 4096, height: float = 0.0):
     """P(p) = sum_m sum_ch w_sar[m] exp(a2 d_hyp) s(a1 d_hyp + f_doppler(p), m, ch).
 
     Alg. 2: d_tx = ||p - q_tx(m, ch)||, d_rx = ||p - q_rx(m, ch)||,
@@ -211,7 +215,8 @@ def bp_alg2(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, a2, chunk: int = 4096):
 
     pix [P, 2]; q_tx, q_rx [M, CH, 2]; f_doppler [P]; s [M, CH, NB] complex;
     w_sar [M].  Returns complex128 [P].  Pixels are processed in chunks only to
-    bound memory; every pixel's sum runs over m in order.
+    bound memory; every pixel's sum runs over m in order.  ``height`` puts the
+    antennas that far above the pixels' plane (3-D distances).
     """
     pix = np.asarray(pix, dtype=np.float64).reshape(-1, 2)
     q_tx = np.asarray(q_tx, dtype=np.float64)
@@ -225,8 +230,8 @@ def bp_alg2(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, a2, chunk: int = 4096):
         p = pix[p0:p0 + chunk]
         acc = np.zeros(p.shape[0], dtype=np.complex128)
         for m in range(M):
-            d_tx = _norm2(p[:, None, :] - q_tx[m][None, :, :])      # [P, CH]
-            d_rx = _norm2(p[:, None, :] - q_rx[m][None, :, :])
+            d_tx = _norm2(p[:, None, :] - q_tx[m][None, :, :], height)      # [P, CH]
+            d_rx = _norm2(p[:, None, :] - q_rx[m][None, :, :], height)
             d_hyp = d_tx + d_rx
             f_ind = a1 * d_hyp + fd[p0:p0 + chunk, None]
             s_hyp = np.exp(a2 * d_hyp)
@@ -236,7 +241,7 @@ def bp_alg2(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, a2, chunk: int = 4096):
     return out
 
 
-def bp_alg2_abs(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, chunk: int = 4096):
+def bp_alg2_abs(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, chunk: int = 4096, height: float = 0.0):
     """Sum of magnitudes of the Alg. 2 terms, sum_m sum_ch |w_sar[m] s(f_ind)|.
 
     Not an image: it is the scale against which the rounding error of a
@@ -254,8 +259,8 @@ def bp_alg2_abs(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, chunk: int = 4096):
         p = pix[p0:p0 + chunk]
         acc = np.zeros(p.shape[0], dtype=np.float64)
         for m in range(M):
-            d_hyp = (_norm2(p[:, None, :] - q_tx[m][None, :, :])
-                     + _norm2(p[:, None, :] - q_rx[m][None, :, :]))
+            d_hyp = (_norm2(p[:, None, :] - q_tx[m][None, :, :], height)
+                     + _norm2(p[:, None, :] - q_rx[m][None, :, :], height))
             f_ind = a1 * d_hyp + fd[p0:p0 + chunk, None]
             val = interp_index(s[m][None, :, :], f_ind[:, :, None])[:, :, 0]
             acc += np.sum(np.abs(val), axis=1) * abs(w[m])
@@ -267,7 +272,7 @@ def bp_alg2_abs(pix, q_tx, q_rx, f_doppler, s, w_sar, a1, chunk: int = 4096):
 # Alg. 1: standard back-projection (per-chirp, per-channel Doppler)
 # ---------------------------------------------------------------------------
 def bp_alg1(pix, q_tx, q_rx, vel, s, w_sar, f0, mu, df, c: float = C_LIGHT,
-            chunk: int = 4096):
+            chunk: int = 4096, height: float = 0.0):
     """Alg. 1 with the chirp-only window vector (Sec. III-B).
 
     For every pixel, chirp m and channel ch: the distances d_tx and d_rx;
@@ -292,8 +297,8 @@ def bp_alg1(pix, q_tx, q_rx, vel, s, w_sar, f0, mu, df, c: float = C_LIGHT,
         for m in range(M):
             r_tx = p[:, None, :] - q_tx[m][None, :, :]
             r_rx = p[:, None, :] - q_rx[m][None, :, :]
-            d_tx = _norm2(r_tx)
-            d_rx = _norm2(r_rx)
+            d_tx = _norm2(r_tx, height)
+            d_rx = _norm2(r_rx, height)
             v_tx = np.sum(r_tx * vel[m], axis=-1) / d_tx
             v_rx = np.sum(r_rx * vel[m], axis=-1) / d_rx
             tau = (d_tx + d_rx) / c

@@ -65,7 +65,7 @@ __device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p) {
   Leg<FORM> l;
   if constexpr (FORM == kBpExact) {
     const float x = p.x - q.x, y = p.y - q.y;
-    l.d = __builtin_amdgcn_sqrtf(fmaf(x, x, y * y));
+    l.d = __builtin_amdgcn_sqrtf(fmaf(x, x, fmaf(y, y, p.z)));  // p.z: squared antenna height
     l.dop = fmaf(x, q.z, y * q.w) * __builtin_amdgcn_rcpf(l.d);
   } else if constexpr (FORM == kBpSplit) {
     const float n = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
@@ -202,15 +202,19 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   out_im = im0 + im1;
 }
 
-__device__ __forceinline__ float box_min_dist(float px, float py, float lx, float ly, float hx, float hy) {
+// nearest and farthest distance from the pixel to an antenna in a box, with
+// the antennas h2 (squared height) above the pixel plane
+__device__ __forceinline__ float box_min_dist(float px, float py, float lx, float ly, float hx, float hy,
+                                              float h2) {
   const float dx = fmaxf(fmaxf(lx - px, px - hx), 0.f);
   const float dy = fmaxf(fmaxf(ly - py, py - hy), 0.f);
-  return sqrtf(dx * dx + dy * dy);
+  return sqrtf(dx * dx + dy * dy + h2);
 }
-__device__ __forceinline__ float box_max_dist(float px, float py, float lx, float ly, float hx, float hy) {
+__device__ __forceinline__ float box_max_dist(float px, float py, float lx, float ly, float hx, float hy,
+                                              float h2) {
   const float dx = fmaxf(fabsf(px - lx), fabsf(px - hx));
   const float dy = fmaxf(fabsf(py - ly), fabsf(py - hy));
-  return sqrtf(dx * dx + dy * dy);
+  return sqrtf(dx * dx + dy * dy + h2);
 }
 
 template <int CHG, int FORM>
@@ -258,10 +262,10 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   // exact form: per term, bounded by f_slack)
   const float fdp = EXACT ? 0.f : (SPLIT ? fi_p - a.a1 * 2.f * p.z : fi_p);
 
-  const float dlo = box_min_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
-                    box_min_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
-  const float dhi = box_max_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y) +
-                    box_max_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y);
+  const float dlo = box_min_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y, a.h2) +
+                    box_min_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y, a.h2);
+  const float dhi = box_max_dist(p.x, p.y, a.tx_lo_x, a.tx_lo_y, a.tx_hi_x, a.tx_hi_y, a.h2) +
+                    box_max_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y, a.h2);
   const float flo = fmaf(a.a1, dlo, fdp), fhi = fmaf(a.a1, dhi, fdp);
   const float mg = a.f_margin + a.f_slack;
   const bool inside = (flo >= mg) & (fhi <= (float)(a.n_bins - 1) - mg);

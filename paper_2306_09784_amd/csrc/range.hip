@@ -17,13 +17,18 @@
 // full-circle twiddle table the host evaluates in double) and writes output r
 // to (b / Ns) Ns R + (b mod Ns) + r Ns.  LDS rows are padded by one element
 // per 16, which keeps the stride-16 writes of the first passes free of bank
-// conflicts.  Rows shorter than 16 x 64 samples share a workgroup.
+// conflicts.  Rows shorter than 16 x 64 samples share a workgroup.  Samples,
+// the range window and twiddles are read through buffer descriptors: the
+// zero padding and the rows past the frame read past the descriptor's range,
+// which returns zeros without a branch.
 #include "rc_kernels.hpp"
 
 namespace rc {
 namespace {
 
 constexpr int kThreads = 256;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
@@ -55,8 +60,9 @@ constexpr int bitrev(int r) {
   return o;
 }
 
-// In-register DFT of R = 2^q points, natural order in and out: radix-2
-// decimation-in-frequency stages, then the bit-reversal as register renaming.
+// In-register DFT of R = 2^q points: radix-2 decimation-in-frequency stages
+// on natural-order input; X[r] ends in v[bitrev(r)] (callers index through
+// bitrev, so the permutation costs nothing).
 template <int R, int S>
 __device__ __forceinline__ void dif_stage(float2* v) {
 #pragma unroll
@@ -83,16 +89,11 @@ __device__ __forceinline__ void dif_stage(float2* v) {
 }
 
 template <int R>
-__device__ __forceinline__ void dft(float2* v) {
+__device__ __forceinline__ void dft_br(float2* v) {
   if constexpr (R >= 16) dif_stage<R, 8>(v);
   if constexpr (R >= 8) dif_stage<R, 4>(v);
   if constexpr (R >= 4) dif_stage<R, 2>(v);
   if constexpr (R >= 2) dif_stage<R, 1>(v);
-  float2 t[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) t[r] = v[bitrev<R>(r)];
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = t[r];
 }
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
@@ -106,22 +107,35 @@ struct Fft {
   static constexpr int PADN = N + N / 16;    // padded LDS row
 };
 
+struct RowIo {
+  __amdgpu_buffer_rsrc_t raw;   // the frame's samples
+  __amdgpu_buffer_rsrc_t win;   // w_range; an index past n_s reads 0
+  __amdgpu_buffer_rsrc_t tw;    // twiddle table
+  unsigned row_off;             // byte offset of this lane's row in raw
+  bool live;
+};
+
 // One Stockham pass of radix R at stride NS over the E samples of this lane
 // (E / R butterflies b = j + T u).
 template <int LOG2N, int R, int NS, bool FIRST, bool LAST>
-__device__ __forceinline__ void fft_pass(const RangeArgs& a, float2* buf, int j, const float2* src, bool live) {
+__device__ __forceinline__ void fft_pass(const RangeArgs& a, const RowIo& io, float2* buf, int j) {
   using F = Fft<LOG2N>;
   constexpr int N = F::N, E = F::E, T = F::T, B = E / R;
   float2 v[E];
   float2 w[E];
   if constexpr (NS > 1) {
     constexpr int lg = __builtin_ctz(NS * R);
-    const int sh = a.tw_log2 - lg;
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int b = j + T * u;
+      // byte offset of W_{NS R}^{(b mod NS) r} in the full-circle table, stepped in r
+      const unsigned step = (unsigned)((b & (NS - 1)) << (a.tw_log2 - lg)) * 8u;
+      unsigned off = step;
 #pragma unroll
-      for (int r = 1; r < R; ++r) w[u * R + r] = a.twiddle[((b & (NS - 1)) * r) << sh];
+      for (int r = 1; r < R; ++r, off += step) {
+        const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(io.tw, off, 0, 0);
+        w[u * R + r] = make_float2(__uint_as_float(t.x), __uint_as_float(t.y));
+      }
     }
   }
 #pragma unroll
@@ -131,13 +145,11 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, float2* buf, int j,
     for (int r = 0; r < R; ++r) {
       const int i = b + r * (N / R);
       if constexpr (FIRST) {
-        float2 x = make_float2(0.f, 0.f);
-        if (live && i < a.n_s) {
-          const float2 z = src[i];
-          const float wr = a.w_range[i];
-          x = make_float2(z.x * wr, z.y * wr);
-        }
-        v[u * R + r] = x;
+        // zero padding and dead rows read past the descriptor, which returns zeros
+        const unsigned off = (io.live && i < a.n_s) ? io.row_off + (unsigned)i * 8u : 0xfffffff0u;
+        const u32x2 z = __builtin_amdgcn_raw_buffer_load_b64(io.raw, off, 0, 0);
+        const float wr = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(io.win, (unsigned)i * 4u, 0, 0));
+        v[u * R + r] = make_float2(__uint_as_float(z.x) * wr, __uint_as_float(z.y) * wr);
       } else {
         v[u * R + r] = buf[pad(i)];
       }
@@ -150,19 +162,23 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, float2* buf, int j,
 #pragma unroll
       for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], w[u * R + r]);
     }
-    dft<R>(v + u * R);
+    dft_br<R>(v + u * R);
   }
 #pragma unroll
   for (int u = 0; u < B; ++u) {
     const int b = j + T * u;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      const float2 x = v[u * R + bitrev<R>(r)];
       if constexpr (LAST) {
-        const int k = b + r * NS;  // natural order after the last pass
-        if (k < a.n_bins) buf[pad(k)] = v[u * R + r];
+        // natural order after the last pass; only the kept bins are stored
+        if (r * NS < a.n_bins) {
+          const int k = b + r * NS;
+          if (k < a.n_bins) buf[pad(k)] = x;
+        }
       } else {
         const int i = (b / NS) * NS * R + (b & (NS - 1)) + r * NS;
-        buf[pad(i)] = v[u * R + r];
+        buf[pad(i)] = x;
       }
     }
   }
@@ -180,16 +196,21 @@ __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeMulti m) 
   const int64_t row = (int64_t)(blockIdx.x - m.begin[fi]) * F::RPW + lrow;
   const bool live = row < a.rows;
   float2* buf = lds + lrow * F::PADN;
-  const float2* src = a.raw + (live ? row : 0) * a.n_s;
+  RowIo io;
+  io.raw = __builtin_amdgcn_make_buffer_rsrc((void*)a.raw, (short)0, (int)(a.rows * a.n_s * 8), kRsrcWord3);
+  io.row_off = (unsigned)(row * a.n_s) * 8u;
+  io.live = live;
+  io.win = __builtin_amdgcn_make_buffer_rsrc((void*)a.w_range, (short)0, a.n_s * 4, kRsrcWord3);
+  io.tw = __builtin_amdgcn_make_buffer_rsrc((void*)a.twiddle, (short)0, 8 << a.tw_log2, kRsrcWord3);
 
   if constexpr (LOG2N < 4) {
-    fft_pass<LOG2N, F::N, 1, true, true>(a, buf, j, src, live);
+    fft_pass<LOG2N, F::N, 1, true, true>(a, io, buf, j);
   } else {
     constexpr int P16 = LOG2N / 4, REM = LOG2N % 4;
-    fft_pass<LOG2N, 16, 1, true, P16 == 1 && REM == 0>(a, buf, j, src, live);
-    if constexpr (P16 >= 2) fft_pass<LOG2N, 16, 16, false, P16 == 2 && REM == 0>(a, buf, j, src, live);
-    if constexpr (P16 >= 3) fft_pass<LOG2N, 16, 256, false, REM == 0>(a, buf, j, src, live);
-    if constexpr (REM > 0) fft_pass<LOG2N, (1 << REM), (1 << (4 * P16)), false, true>(a, buf, j, src, live);
+    fft_pass<LOG2N, 16, 1, true, P16 == 1 && REM == 0>(a, io, buf, j);
+    if constexpr (P16 >= 2) fft_pass<LOG2N, 16, 16, false, P16 == 2 && REM == 0>(a, io, buf, j);
+    if constexpr (P16 >= 3) fft_pass<LOG2N, 16, 256, false, REM == 0>(a, io, buf, j);
+    if constexpr (REM > 0) fft_pass<LOG2N, (1 << REM), (1 << (4 * P16)), false, true>(a, io, buf, j);
   }
 
   if (!live) return;
@@ -243,7 +264,8 @@ hipError_t launch_range_compress(const RangeMulti& m, hipStream_t s) {
     const RangeArgs& a = m.f[i];
     if (a.rows < 0 || a.n_fft < 4 || (a.n_fft & (a.n_fft - 1)) || (1 << a.log2n) != a.n_fft ||
         a.n_fft > 4096 || a.log2n != log2n || a.n_s < 1 || a.n_s > a.n_fft || a.n_bins < 1 ||
-        a.n_bins > a.n_fft || a.n_ch < 1 || a.tw_log2 < a.log2n || a.tw_log2 > 12)
+        a.n_bins > a.n_fft || a.n_ch < 1 || a.tw_log2 < a.log2n || a.tw_log2 > 12 ||
+        a.rows * a.n_s * 8 >= (int64_t(1) << 31))
       return hipErrorInvalidValue;
   }
   switch (log2n) {

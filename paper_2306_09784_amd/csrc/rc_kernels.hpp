@@ -61,13 +61,15 @@ struct PairArgs {
 using PairMulti = Multi<PairArgs, 32>;
 hipError_t launch_spectrum_pairs(const PairMulti& m, hipStream_t s);
 
-// Per-pixel tables, evaluated in double and rounded once:
+// Per-pixel tables, evaluated in double and rounded once (h: the antenna
+// height above the pixel plane in wavelengths, 0 for planar geometry; R^2 =
+// |P|^2 + h^2 the squared distance to the aperture centre):
 //  * f_doppler(p) in bins from the mean velocity at the aperture centre;
 //  * the pixel in aperture-local wavelength units, P = (p - c) / lambda, as
-//    float4 (P'.x, P'.y, pp, corr) with P' = float(P), pp = float(|P|^2) and
-//    corr = (|P|^2 - pp) / |P|, the first-order path correction (in turns) for
+//    float4 (P'.x, P'.y, pp, corr) with P' = float(P), pp = float(R^2) and
+//    corr = (R^2 - pp) / R, the first-order path correction (in turns) for
 //    the rounding of pp that back-projection adds to every two-way path;
-//  * exact-Doppler form: (P'.x, P'.y, 0, corr) with corr = 2 <P, P - P'> / |P|,
+//  * exact-Doppler form: (P'.x, P'.y, h^2, corr) with corr = 2 <P, P - P'> / R,
 //    the first-order correction for the rounding of P itself.
 struct TableArgs {
   const float2* pix;
@@ -85,6 +87,7 @@ struct TableArgs {
   int exact;
   double a1;                      // bins per wavelength of path
   float* fbase;                   // [n_pix] (split only)
+  double height;                  // antennas above the pixel plane, metres
 };
 using TableMulti = Multi<TableArgs, 16>;
 hipError_t launch_pixel_tables(const TableMulti& m, hipStream_t s);
@@ -131,6 +134,7 @@ struct BpFrame {
   float rx_lo_x, rx_lo_y, rx_hi_x, rx_hi_y;
   float f_margin;
   float f_slack;          // largest |Doppler index| a term can carry (exact form)
+  float h2;               // (antenna height / wavelength)^2 (0: planar geometry)
 };
 
 constexpr int kBpMaxFrames = 16;  // frames per launch (descriptors travel as kernel arguments)
@@ -199,7 +203,8 @@ struct RecheckArgs {
   double a1;                // bins per metre of two-way path
   double kd;                // bins per m/s of radial speed
   double inv_lam;           // turns per metre of path
-  double qt_x, qt_y, qr_x, qr_y, v_x, v_y;  // aperture centre and mean velocity (Doppler table)
+  double qt_x, qt_y, qr_x, qr_y, v_x, v_y;  // mean TX and RX positions and mean velocity (Doppler table)
+  double height;            // antennas above the pixel plane, metres
   double* power;            // [cap][(2 half + 1)^2] scratch
   unsigned long long* mask;
   int words_per_row;

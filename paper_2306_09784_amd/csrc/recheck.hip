@@ -24,10 +24,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// distance from the antenna at q (h2 = squared height above the pixel plane)
+// to the pixel, and the radial speed of a horizontal velocity along it
 __device__ __forceinline__ double radial(double px, double py, double qx, double qy, double vx, double vy,
-                                         double* d) {
+                                         double h2, double* d) {
   const double rx = px - qx, ry = py - qy;
-  *d = sqrt(rx * rx + ry * ry);
+  *d = sqrt(rx * rx + ry * ry + h2);
   return *d > 0.0 ? (rx * vx + ry * vy) / *d : 0.0;
 }
 
@@ -49,10 +51,12 @@ __global__ __launch_bounds__(kThreads) void recheck_pixels_kernel(RecheckArgs a)
     const int r = cell / a.n_cols + dr, c = cell % a.n_cols + dc;  // inside: tested cells have full windows
     const float2 pf = a.pix[(int64_t)r * a.n_cols + c];
     const double px = pf.x, py = pf.y;
+    const double h2 = a.height * a.height;
     double fd = 0.0;
     if (!a.exact) {
       double d0;
-      fd = a.kd * (radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, &d0) + radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y, &d0));
+      fd = a.kd * (radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, h2, &d0) +
+                   radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y, h2, &d0));
     }
     double acc_re = 0.0, acc_im = 0.0;
     for (int t = threadIdx.x; t < rows; t += kThreads) {
@@ -62,13 +66,13 @@ __global__ __launch_bounds__(kThreads) void recheck_pixels_kernel(RecheckArgs a)
       double d_tx, d_rx, f;
       if (a.exact) {
         const float2 v = a.vel[m];
-        const double vt = radial(px, py, q.x, q.y, v.x, v.y, &d_tx);
-        const double vr = radial(px, py, q.z, q.w, v.x, v.y, &d_rx);
+        const double vt = radial(px, py, q.x, q.y, v.x, v.y, h2, &d_tx);
+        const double vr = radial(px, py, q.z, q.w, v.x, v.y, h2, &d_rx);
         f = a.a1 * (d_tx + d_rx) + a.kd * (vt + vr);
       } else {
         const double tx = px - q.x, ty = py - q.y, rx = px - q.z, ry = py - q.w;
-        d_tx = sqrt(tx * tx + ty * ty);
-        d_rx = sqrt(rx * rx + ry * ry);
+        d_tx = sqrt(tx * tx + ty * ty + h2);
+        d_rx = sqrt(rx * rx + ry * ry + h2);
         f = a.a1 * (d_tx + d_rx) + fd;
       }
       if (!(f >= 0.0 && f <= (double)(a.n_bins - 1))) continue;

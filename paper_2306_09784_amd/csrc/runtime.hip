@@ -244,6 +244,7 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
   if (f.n_rows > 65535 * 16)
     return fail(RC_EINVAL, "frame %lld: n_rows %d too large", (long long)f.frame_id, f.n_rows);
   if (!(f.fs > 0)) return fail(RC_EINVAL, "frame %lld: fs must be positive", (long long)f.frame_id);
+  if (!std::isfinite(f.height)) return fail(RC_EINVAL, "frame %lld: height must be finite", (long long)f.frame_id);
   if (!f.data || !f.q_tx || !f.q_rx || !f.vel || !f.pixels)
     return fail(RC_EINVAL, "frame %lld: data, q_tx, q_rx, vel and pixels are required", (long long)f.frame_id);
   const int64_t rows = (int64_t)f.n_chirps * f.n_channels;
@@ -447,6 +448,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
   ta.exact = exact;
   ta.a1 = a1 * lam;
   ta.fbase = s.fbase;
+  ta.height = f.height;
 
   // back-projection descriptor (Alg. 2), launched batch-wide by the caller
   float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
@@ -476,6 +478,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
   // single-precision error of an index a1 d_hyp + f_doppler <= n_bins is a few
   // ulps of n_bins; the margin keeps such waves on the range-tested path
   ba.f_margin = (float)(1e-3 + 64.0 * f.n_bins * std::ldexp(1.0, -24));
+  ba.h2 = (float)(f.height * inv_lam * f.height * inv_lam);
   if (n_kb > 1 && (int64_t)n_kb * n_pix > s.partial_cap)
     return fail(RC_EINVAL, "frame %lld: %d chirp blocks of %lld pixels exceed the slot's partial buffer",
                 (long long)f.frame_id, n_kb, (long long)n_pix);
@@ -498,6 +501,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
     rk.qt_x = ta.qt_x; rk.qt_y = ta.qt_y;
     rk.qr_x = ta.qr_x; rk.qr_y = ta.qr_y;
     rk.v_x = vx; rk.v_y = vy;
+    rk.height = f.height;
   }
   out->chg = chg;
   s.busy = true;

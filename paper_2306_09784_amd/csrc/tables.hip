@@ -28,10 +28,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// radial speed towards the pixel of a (horizontal) velocity at q, the antenna
+// h2 = height^2 above the pixel plane
 __device__ __forceinline__ double radial(double px, double py, double qx, double qy, double vx,
-                                         double vy) {
+                                         double vy, double h2) {
   const double rx = px - qx, ry = py - qy;
-  const double d = sqrt(rx * rx + ry * ry);
+  const double d = sqrt(rx * rx + ry * ry + h2);
   return d > 0.0 ? (rx * vx + ry * vy) / d : 0.0;
 }
 
@@ -42,17 +44,21 @@ __global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableMulti m) {
   if (i >= a.n_pix) return;
   const float2 p = a.pix[i];
   const double px = p.x, py = p.y;
-  const double r = radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y) +
-                   radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y);
+  const double h2m = a.height * a.height;
+  const double r = radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, h2m) +
+                   radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y, h2m);
   a.fd[i] = (float)(a.kd * r);
   const double lx = (px - a.c_x) * a.inv_lam, ly = (py - a.c_y) * a.inv_lam;
-  const double pp = lx * lx + ly * ly;
+  const double hl = a.height * a.inv_lam;
+  // |P|^2 + h^2: the squared distance to the aperture centre, which carries the
+  // antenna height into every distance back-projection forms
+  const double pp = lx * lx + ly * ly + hl * hl;
   const float ppf = (float)pp;
   const double R = sqrt(pp);
   if (a.exact) {
     const float fx = (float)lx, fy = (float)ly;
     const double corr = R > 0.0 ? 2.0 * (lx * (lx - fx) + ly * (ly - fy)) / R : 0.0;
-    a.pixc[i] = make_float4(fx, fy, 0.f, (float)corr);
+    a.pixc[i] = make_float4(fx, fy, (float)(hl * hl), (float)corr);
   } else if (a.split) {
     const double two_r = 2.0 * R;
     a.pixc[i] = make_float4((float)lx, (float)ly, (float)R, (float)(two_r - floor(two_r)));

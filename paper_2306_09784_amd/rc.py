@@ -16,7 +16,7 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librc.so")
 
-RC_ABI_VERSION = 1
+RC_ABI_VERSION = 2
 
 # rc_status
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_ETRUNC, RC_EHIP, RC_ENOTREADY, RC_ENOTFOUND = range(7)
@@ -89,6 +89,7 @@ class rc_frame(C.Structure):
         ("image_out", C.c_void_p),
         ("doppler_out", C.c_void_p),
         ("spectrum_out", C.c_void_p),
+        ("height", C.c_double),
     ]
 
 
@@ -292,7 +293,7 @@ class Plan:
     def make_frame(frame_id: int, *, data, q_tx: np.ndarray, q_rx: np.ndarray, vel: np.ndarray,
                    pixels, n_rows: int, n_cols: int, n_bins: int, n_fft: int, fs: float,
                    n_samples: int = 0, input_kind: int = RC_INPUT_RAW, image_out=None,
-                   doppler_out=None, spectrum_out=None, sensor_id: int = 0) -> rc_frame:
+                   doppler_out=None, spectrum_out=None, sensor_id: int = 0, height: float = 0.0) -> rc_frame:
         """Builds an rc_frame.  q_tx, q_rx, vel must be C-contiguous float32
         host arrays that stay alive until rc_process_batch returns."""
         for a in (q_tx, q_rx, vel):
@@ -304,7 +305,7 @@ class Plan:
         return rc_frame(frame_id, sensor_id, n_samples, n_fft, n_bins, M, CH, fs, input_kind,
                         _ptr(data), q_tx.ctypes.data, q_rx.ctypes.data, vel.ctypes.data,
                         _ptr(pixels), n_rows, n_cols, _ptr(image_out), _ptr(doppler_out),
-                        _ptr(spectrum_out))
+                        _ptr(spectrum_out), float(height))
 
     def process(self, frames, stream=None) -> int:
         arr = (rc_frame * len(frames))(*frames)

@@ -95,7 +95,8 @@ class Server:
                 descs.append(_rc.Plan.make_frame(
                     fid, data=dst, q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel, pixels=sens.pix_dev,
                     n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
-                    n_samples=fr.cfg.n_samples, image_out=img, sensor_id=sens.sensor_id))
+                    n_samples=fr.cfg.n_samples, image_out=img, sensor_id=sens.sensor_id,
+                    height=fr.cfg.height))
                 self.inflight[fid] = (slot, sens.sensor_id, arrival, now)
         self.plan.process(descs, stream)
 

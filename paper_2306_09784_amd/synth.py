@@ -60,6 +60,7 @@ class SceneConfig:
     ny: int = 256
     speed: Optional[float] = None  # m/s; None draws U[1, 9]
     yaw_rate: float = 0.0          # rad/s, 0 = straight path
+    height: float = 0.0            # radar above the ground plane of targets and pixels, m
     n_targets: int = 8
     snr_db: tuple = (10.0, 30.0)
     n_clutter: int = 0             # extended clutter patches
@@ -188,8 +189,9 @@ def required_bins(cfg: SceneConfig, q_tx, q_rx, vel, radar=RADAR, margin: int = 
     corners = np.array([[x0, y0], [x0, y1], [x1, y0], [x1, y1]])
     qt = q_tx.reshape(-1, 2)
     qr = q_rx.reshape(-1, 2)
-    dmax = (np.sqrt(((corners[:, None, :] - qt[None]) ** 2).sum(-1)).max()
-            + np.sqrt(((corners[:, None, :] - qr[None]) ** 2).sum(-1)).max())
+    h2 = cfg.height ** 2
+    dmax = (np.sqrt(((corners[:, None, :] - qt[None]) ** 2).sum(-1) + h2).max()
+            + np.sqrt(((corners[:, None, :] - qr[None]) ** 2).sum(-1) + h2).max())
     vmax = float(np.sqrt((vel ** 2).sum(-1)).max())
     fmax = mu * dmax / radar["c"] + 2.0 * radar["f0"] * vmax / radar["c"]
     nb = int(math.ceil(fmax / df)) + margin
@@ -197,11 +199,13 @@ def required_bins(cfg: SceneConfig, q_tx, q_rx, vel, radar=RADAR, margin: int = 
 
 
 def beat_signal(scat_pos, scat_amp, q_tx, q_rx, vel, n_samples: int, fs: float,
-                radar=RADAR, device: str = "cpu", chunk: Optional[int] = None):
+                radar=RADAR, device: str = "cpu", chunk: Optional[int] = None, height: float = 0.0):
     """Noise-free beat signal complex128 [M, CH, n_samples] as a torch tensor.
 
     Evaluated in float64 on ``device``; the carrier phase f0 tau is reduced to
-    its fractional cycle before it is scaled by 2 pi.
+    its fractional cycle before it is scaled by 2 pi.  Scatterers lie on the
+    ground plane, the antennas ``height`` above it (3-D distances; the
+    horizontal velocity projects on the 3-D line of sight).
     """
     import torch
 
@@ -225,8 +229,8 @@ def beat_signal(scat_pos, scat_amp, q_tx, q_rx, vel, n_samples: int, fs: float,
         a = torch.as_tensor(amp[s0:s0 + chunk], dtype=torch.complex128, device=dev)
         rt = x - qt[None]
         rr = x - qr[None]
-        dt = torch.sqrt((rt * rt).sum(-1))
-        dr = torch.sqrt((rr * rr).sum(-1))
+        dt = torch.sqrt((rt * rt).sum(-1) + height * height)
+        dr = torch.sqrt((rr * rr).sum(-1) + height * height)
         tau = (dt + dr) / c
         fdop = f0 / c * ((rt * v[None]).sum(-1) / dt + (rr * v[None]).sum(-1) / dr)
         ph0 = torch.remainder(f0 * tau, 1.0)                     # [S, M, CH]
@@ -275,7 +279,7 @@ def make_frame(cfg: SceneConfig, frame_index: int = 0, device: str = "cpu",
     vel32 = vel.astype(np.float32)
     pos, amp, tpos, tamp = _scatterers(cfg, rng)
     fs = sample_rate(cfg, radar)
-    sig = beat_signal(pos, amp, q_tx32, q_rx32, vel32, cfg.n_samples, fs, radar, device)
+    sig = beat_signal(pos, amp, q_tx32, q_rx32, vel32, cfg.n_samples, fs, radar, device, height=cfg.height)
     raw = sig.to("cpu").numpy()
     if cfg.noise:
         nrng = np.random.default_rng(2000 + frame_index)

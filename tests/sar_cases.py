@@ -60,7 +60,7 @@ def run_gpu(rc, plan, frame, torch, frame_id=1, spectrum=None, want_spectrum=Fal
                             pixels=t["pix"], n_rows=frame.n_rows, n_cols=frame.n_cols,
                             n_bins=frame.n_bins, n_fft=frame.n_fft, fs=frame.fs,
                             n_samples=frame.cfg.n_samples, input_kind=kind, image_out=img,
-                            doppler_out=dop_out, spectrum_out=spec_out)
+                            doppler_out=dop_out, spectrum_out=spec_out, height=frame.cfg.height)
     plan.process([fr])
     dets = plan.detections(frame_id)
     torch.cuda.synchronize()
@@ -91,12 +91,13 @@ def run_oracle(frame, spectrum=None, pix_index=None, sar_window="hann", range_wi
     pix = frame.pix.astype(np.float64)
     if pix_index is not None:
         pix = pix[pix_index]
-    fd = O.doppler_table(pix, frame.q_tx, frame.q_rx, frame.vel, k["kd"])
+    h = frame.cfg.height
+    fd = O.doppler_table(pix, frame.q_tx, frame.q_rx, frame.vel, k["kd"], height=h)
     w = O.window(sar_window, frame.cfg.n_chirps)
     if doppler == "exact":
-        P = O.bp_alg1(pix, frame.q_tx, frame.q_rx, frame.vel, s, w, R["f0"], k["mu"], k["df"])
+        P = O.bp_alg1(pix, frame.q_tx, frame.q_rx, frame.vel, s, w, R["f0"], k["mu"], k["df"], height=h)
     else:
-        P = O.bp_alg2(pix, frame.q_tx, frame.q_rx, fd, s, w, k["a1"], k["a2"])
+        P = O.bp_alg2(pix, frame.q_tx, frame.q_rx, fd, s, w, k["a1"], k["a2"], height=h)
     out = {"spectrum": s, "doppler": fd, "image": P, "w_sar": w, "k": k}
     if pix_index is None and cfar is not None:
         pw = (np.abs(P) ** 2).reshape(frame.n_rows, frame.n_cols)

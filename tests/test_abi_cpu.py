@@ -55,7 +55,7 @@ int main(void) {
   P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision) P(rc_plan_desc, doppler)
   P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, max_rechecks) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
   P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
-  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out)
+  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out) P(rc_frame, height)
   P(rc_detection, threshold) P(rc_detection, flags)
   return 0;
 }

@@ -72,7 +72,7 @@ def _phase_bound(frame, precision):
         return 2.0 ** -19 * Q / lam + 2e-6
     corners = np.array([[frame.pix[:, 0].min(), frame.pix[:, 1].min()], [frame.pix[:, 0].max(), frame.pix[:, 1].max()],
                         [frame.pix[:, 0].min(), frame.pix[:, 1].max()], [frame.pix[:, 0].max(), frame.pix[:, 1].min()]])
-    d_max = 2 * np.sqrt(((corners[:, None, :] - q[None]) ** 2).sum(-1)).max()
+    d_max = 2 * np.sqrt(((corners[:, None, :] - q[None]) ** 2).sum(-1) + frame.cfg.height ** 2).max()
     return 2.0 ** -21 * d_max / lam + 1e-5
 
 
@@ -80,7 +80,8 @@ def _amp_bound(frame, ora, precision, pix_index=None):
     """Per-pixel bound on |P_gpu - P_oracle| (see module docstring)."""
     k = ora["k"]
     pix = frame.pix.astype(np.float64) if pix_index is None else frame.pix.astype(np.float64)[pix_index]
-    S = O.bp_alg2_abs(pix, frame.q_tx, frame.q_rx, ora["doppler"], ora["spectrum"], ora["w_sar"], k["a1"])
+    S = O.bp_alg2_abs(pix, frame.q_tx, frame.q_rx, ora["doppler"], ora["spectrum"], ora["w_sar"], k["a1"],
+                      height=frame.cfg.height)
     gamma = (frame.cfg.n_chirps * frame.cfg.n_channels / 2 + 2) * 2.0 ** -24
     pmax = np.abs(ora["image"]).max()
     return (2 * math.pi * _phase_bound(frame, precision) + gamma) * S + BP_FLOOR * pmax
@@ -225,6 +226,23 @@ def test_end_to_end_exact_doppler(rc, torch):
         out = SC.run_gpu(rc, plan, fr, torch)
     ora = SC.run_oracle(fr, cfar=None, doppler="exact")
     _check_image("end_to_end_exact", fr, out["image"], ora, PLAIN)
+
+
+@pytest.mark.parametrize("precision,doppler", [(PLAIN, 0), (SPLIT, 0), (PLAIN, 1)], ids=["fp32", "split", "exact"])
+def test_antenna_height(rc, torch, precision, doppler):
+    """Antennas 0.8 m above the pixel plane (3-D distances): every form against
+    the oracle with the same height, on a scene simulated with that height."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="height", n_samples=128, n_chirps=48, n_rx=4,
+                              nx=48, ny=40, box=(-3.0, 3.0, 1.0, 6.0), n_targets=4, height=0.8, seed=31,
+                              yaw_rate=0.4 if doppler else 0.0)
+    fr = synth.make_frame(cfg)
+    kw = dict(precision=precision, doppler=rc.RC_DOPPLER_EXACT if doppler else rc.RC_DOPPLER_AVERAGE)
+    with rc.Plan(SC.plan_config(rc, [fr], **kw)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, want_doppler=not doppler)
+    ora = SC.run_oracle(fr, cfar=None, doppler="exact" if doppler else "average")
+    if not doppler:
+        assert np.abs(out["doppler"] - ora["doppler"]).max() <= DOP_TOL
+    _check_image(f"height_{['avg', 'exact'][doppler]}", fr, out["image"], ora, precision)
 
 
 @pytest.mark.parametrize("n_rows,n_cols", [(1, 300), (5, 70), (8, 8), (9, 17)])

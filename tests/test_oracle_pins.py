@@ -4,6 +4,7 @@ Each test names the pin it checks: figures the paper prints, closed forms,
 library routines the oracle does not call, brute force on tiny inputs and
 invariants of back-projection.  CPU only.
 """
+import dataclasses
 import json
 import math
 import os
@@ -349,6 +350,61 @@ def test_point_target_focuses_and_rx_halving_costs_6db():
     assert loss == pytest.approx(20 * np.log10(2), abs=0.05)
     Pb = O.bp_alg2(pix[:1], fr.q_tx[:, h:], fr.q_rx[:, h:], fd[:1], s[:, h:], w, k["a1"], k["a2"])
     assert Ph[0] + Pb[0] == pytest.approx(P[0], rel=1e-12)
+
+
+def test_bp_closed_form_coherent_gain_with_height():
+    """P1 with the antennas h above the pixel plane: s matched to the 3-D paths
+    of p0 focuses to exactly N_ch sum(w); Alg. 1 agrees on a static aperture."""
+    q_tx, q_rx, vel = _geometry(M=16, CH=2)
+    M, CH, _ = q_tx.shape
+    h = 0.9
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    rng = np.random.default_rng(13)
+    pix = np.stack([rng.uniform(-3, 3, 20), rng.uniform(3, 8, 20)], -1)
+    p0 = 5
+    d3 = lambda p, q: np.sqrt(np.sum((p - q) ** 2, axis=-1) + h * h)  # noqa: E731
+    dh0 = d3(pix[p0], q_tx) + d3(pix[p0], q_rx)
+    f0 = k["a1"] * dh0
+    kk = np.arange(160.0)
+    s = np.exp(2j * np.pi * dh0 / k["lam"])[:, :, None] * (1 + 0.01 * (kk[None, None, :] - f0[:, :, None]))
+    w = O.window("hann", M) + 0.1
+    P = O.bp_alg2(pix, q_tx, q_rx, np.zeros(20), s, w, k["a1"], k["a2"], height=h)
+    assert P[p0] == pytest.approx(CH * w.sum(), rel=1e-9)
+    # Alg. 1 at zero velocity with the same height gives Alg. 2's image
+    P1 = O.bp_alg1(pix, q_tx, q_rx, np.zeros_like(vel), s, w, R["f0"], k["mu"], k["df"], height=h)
+    np.testing.assert_allclose(P1, P, rtol=1e-9, atol=1e-9 * abs(P[p0]))
+
+
+def test_doppler_table_with_height_closed_form():
+    """A pixel on the line of motion at distance x from the (co-located) aperture
+    centre, antennas h above the plane: f_d = kd 2 v x / sqrt(x^2 + h^2)."""
+    h, v, x, kd = 1.2, 3.0, 4.0, 37.5
+    q = np.zeros((2, 1, 2))
+    vel = np.array([[v, 0.0], [v, 0.0]])
+    fd = O.doppler_table(np.array([[x, 0.0], [-x, 0.0], [0.0, 5.0]]), q, q, vel, kd, height=h)
+    assert fd[0] == pytest.approx(kd * 2 * v * x / math.hypot(x, h), rel=1e-14)
+    assert fd[1] == pytest.approx(-fd[0], rel=1e-14)
+    assert fd[2] == 0.0
+
+
+def test_point_target_with_height_focuses_only_with_it():
+    """A point target simulated with the radar 1 m above the ground focuses at its
+    position when back-projected with that height, and loses gain without it."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="h", n_samples=128, n_chirps=64, n_rx=4,
+                              nx=9, ny=9, box=(-0.4, 0.4, 2.6, 3.4), n_targets=1, noise=False, height=1.0,
+                              speed=4.0, seed=77)
+    fr = synth.make_frame(cfg)
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], fr.fs, fr.n_fft)
+    s = O.range_compress(fr.raw, O.window("hann", cfg.n_samples), fr.n_fft, fr.n_bins)
+    w = O.window("hann", cfg.n_chirps)
+    tp = fr.targets[0][None, :]
+    amp = {}
+    for h in (1.0, 0.0):
+        fd = O.doppler_table(tp, fr.q_tx, fr.q_rx, fr.vel, k["kd"], height=h)
+        amp[h] = abs(O.bp_alg2(tp, fr.q_tx, fr.q_rx, fd, s, w, k["a1"], k["a2"], height=h)[0])
+    bound = abs(fr.target_amp[0]) * cfg.n_channels * w.sum() * O.window("hann", cfg.n_samples).sum()
+    assert 0.5 * bound < amp[1.0] <= bound
+    assert amp[0.0] < 0.7 * amp[1.0]            # the planar reading loses more than 3 dB
 
 
 def test_doppler_average_error_below_100hz():
