@@ -175,8 +175,12 @@ def cpu_baseline(frame, budget_s: float = 20.0, procs: int = 16):
 
 
 def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup,
-                  doppler=0, want_image=False):
-    """Times `steps` frames through rc_process_batch + rc_detections on one stream."""
+                  doppler=0, want_image=False, depth=2):
+    """Times `steps` frames through rc_process_batch + rc_detections on one
+    stream, `depth` frames in flight: frame i + 1 is prepared on the host and
+    enqueued while the GPU still processes frame i (a sensor streams frames
+    back to back).  Latency is per frame, from its submission to its
+    detections on the host."""
     dev = torch.device("cuda:0")
     cfg = frame.cfg
     raw = torch.from_numpy(frame.raw).to(dev)
@@ -185,32 +189,38 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
     img = torch.empty((n_pix, 2), dtype=torch.float32, device=dev)
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
                        n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
-                       n_pix_max=n_pix, max_frames_in_flight=2, max_detections=1 << 16,
+                       n_pix_max=n_pix, max_frames_in_flight=max(2, depth), max_detections=1 << 16,
                        precision=precision, doppler=doppler, stage_timing=True)
     stream = torch.cuda.current_stream()
     lat, stages, n_det = [], [], 0
     with rc.Plan(pc) as plan:
-        def step(fid):
+        def submit(fid):
             fr = rc.Plan.make_frame(fid, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
                                     n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins, n_fft=frame.n_fft,
                                     fs=frame.fs, n_samples=cfg.n_samples, image_out=img, height=cfg.height)
             plan.process([fr], stream)
-            return plan.detections(fid)
 
         for i in range(warmup):
-            step(i)
+            submit(i)
+            plan.detections(i)
             plan.release(i)
         torch.cuda.synchronize()
         with no_gc():
             t_start = time.perf_counter()
+            t_sub = {}
+            queue = []
             for i in range(steps):
                 fid = 1000 + i
-                t0 = time.perf_counter()
-                dets = step(fid)
-                lat.append(time.perf_counter() - t0)
-                stages.append(plan.stage_times(fid))
-                plan.release(fid)
-                n_det = len(dets)
+                t_sub[fid] = time.perf_counter()
+                submit(fid)
+                queue.append(fid)
+                while len(queue) >= depth or (i == steps - 1 and queue):
+                    done = queue.pop(0)
+                    dets = plan.detections(done)
+                    lat.append(time.perf_counter() - t_sub[done])
+                    stages.append(plan.stage_times(done))
+                    plan.release(done)
+                    n_det = len(dets)
             torch.cuda.synchronize()
             total = time.perf_counter() - t_start
     res = {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
@@ -349,6 +359,15 @@ def mixed_plan_config(rc, synth, sensors, slots, **kw):
                          max_detections=1 << 14, **kw)
 
 
+def batched_mixed_median(rc, synth, torch, sensors, repeats=3, **kw):
+    """batched_mixed repeated; the run with the median throughput, plus every run's."""
+    runs = [batched_mixed(rc, synth, torch, sensors, **kw) for _ in range(repeats)]
+    runs.sort(key=lambda r: r["frames_per_s"])
+    med = dict(runs[len(runs) // 2])
+    med["frames_per_s_runs"] = [r["frames_per_s"] for r in runs]
+    return med
+
+
 def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32):
     """Frames of mixed sizes in batches of `batch` frames per rc_process_batch
     (one back-projection launch per TX-group width and 16 frames), each batch
@@ -459,7 +478,7 @@ def main(argv=None):
 
     if args.batched_only:
         sensors = make_sensors(rc, synth, torch, 32)
-        print(json.dumps({"batched_mixed": batched_mixed(rc, synth, torch, sensors)}), flush=True)
+        print(json.dumps({"batched_mixed": batched_mixed_median(rc, synth, torch, sensors)}), flush=True)
         return 0
     cfg = synth.CONFIGS[args.workload]
     t0 = time.perf_counter()
@@ -467,6 +486,9 @@ def main(argv=None):
     t_synth = time.perf_counter() - t0
     main_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
                              rc.RC_PREC_FP32, args.steps, args.warmup)
+    # frame latency alone (one frame in flight)
+    lat_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
+                            rc.RC_PREC_FP32, 10, 1, depth=1)
     stages = main_run["stages"]
     n_pix = frame.n_rows * frame.n_cols
     progress(f"main workload: {main_run['fps']:.1f} frames/s")
@@ -481,7 +503,7 @@ def main(argv=None):
     range_bytes = float(M * CH) * (8 * cfg.n_samples + 8 * frame.n_bins)
     range_ms = float(stages[:, 0].mean())
     total = main_run["total_s"]
-    lat = main_run["lat"]
+    lat = lat_run["lat"]
     out = {
         "metric": METRIC,
         "value": args.steps / total,
@@ -492,6 +514,9 @@ def main(argv=None):
         "ms_per_step": 1e3 * total / args.steps,
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "latency_note": "p50/p99: submission to detections on the host, one frame in flight (10 frames); "
+                        "value and ms_per_step: frames streamed back to back, two in flight",
+        "streamed_p50_ms": 1e3 * float(np.percentile(main_run["lat"], 50)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -534,7 +559,7 @@ def main(argv=None):
         out["tab2_ablation"] = ablation(rc, synth, torch)
         progress("Tab. II ablation done")
         sensors = make_sensors(rc, synth, torch, 32)
-        out["batched_mixed"] = batched_mixed(rc, synth, torch, sensors)
+        out["batched_mixed"] = batched_mixed_median(rc, synth, torch, sensors)
         progress(f"batched mixed: {out['batched_mixed']['frames_per_s']:.0f} frames/s")
         if args.serve_seconds > 0:
             out["serving"] = serving(rc, synth, torch, sensors, out["batched_mixed"]["frames_per_s"],
