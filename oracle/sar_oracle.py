@@ -30,7 +30,11 @@ design notes of the repository):
 * f_doppler is in bins, taken at the aperture centre (mean TX and mean RX
   position over all chirps and channels) with the mean velocity; a velocity
   pointing towards the pixel gives a positive shift, as in Alg. 1.
-* Geometry is planar (2-D distances).
+* Geometry is planar (2-D distances) unless a radar height above the pixels'
+  plane is given (3-D distances, the pixels' plane below the antennas).
+* Continuous SAR (Sec. V): an aperture is the last n_sub sub-apertures of a
+  sensor's chirp stream, windowed over all of its chirps; with the averaged
+  Doppler each sub-aperture uses its own Doppler table.
 * The CA-CFAR detector is not part of the paper; it is the detection stage
   layered on the image: square-law cell-averaging over the 2-D pixel lattice.
 """
@@ -50,6 +54,7 @@ __all__ = [
     "bp_alg2",
     "bp_alg1",
     "bp_alg2_abs",
+    "bp_sliding",
     "cartesian_grid",
     "polar_grid_params",
     "polar_grid",
@@ -307,6 +312,48 @@ def bp_alg1(pix, q_tx, q_rx, vel, s, w_sar, f0, mu, df, c: float = C_LIGHT,
             val = interp_index(s[m][None, :, :], (f_hyp / df)[:, :, None])[:, :, 0]
             acc += np.sum(s_hyp * val, axis=1) * w[m]
         out[p0:p0 + chunk] = acc
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Continuous SAR: overlapping apertures of one sensor's chirp stream (Sec. V)
+# ---------------------------------------------------------------------------
+def bp_sliding(pix, blocks, b, n_sub, a1, a2, kd, window_kind="hann", doppler="average",
+               f0=None, mu=None, df=None, c: float = C_LIGHT, height: float = 0.0):
+    """Image of the aperture that ends with sub-aperture ``b`` of a stream.
+
+    The conclusion (Sec. V) argues that a continuous measurement can be imaged
+    as it arrives.  Reading taken here: a sensor's chirp stream is cut into
+    sub-apertures of S chirps each; the aperture of sub-aperture b is the last
+    ``n_sub`` of them (N = n_sub S chirps, sub-apertures b - n_sub + 1 .. b),
+    weighted by the chirp window over N positions (Sec. III-B) with chirp i of
+    sub-aperture j at position (j - (b - n_sub + 1)) S + i.  Sub-apertures
+    before the start of the stream (j < 0) hold no chirps and add nothing.
+    With the averaged Doppler (Alg. 2) each sub-aperture's terms use the
+    Doppler table of that sub-aperture (its mean positions and velocity,
+    Sec. III-D); with doppler="exact" each term has its own (Alg. 1).
+
+    blocks[j]: dict with q_tx, q_rx [S, CH, 2], vel [S, 2] and s [S, CH, NB]
+    (the beat spectrum of those chirps).  Alg. 1 needs f0, mu and df.
+    Returns complex128 [P].
+    """
+    pix = np.asarray(pix, dtype=np.float64).reshape(-1, 2)
+    S = int(np.asarray(blocks[b]["s"]).shape[0])
+    N = n_sub * S
+    w = window(window_kind, N)
+    first = b - n_sub + 1
+    out = np.zeros(pix.shape[0], dtype=np.complex128)
+    for j in range(max(first, 0), b + 1):
+        blk = blocks[j]
+        if np.asarray(blk["s"]).shape[0] != S:
+            raise ValueError("every sub-aperture of a stream has the same chirp count")
+        w_j = w[(j - first) * S:(j - first + 1) * S]
+        if doppler == "exact":
+            out += bp_alg1(pix, blk["q_tx"], blk["q_rx"], blk["vel"], blk["s"], w_j, f0, mu, df, c=c,
+                           height=height)
+        else:
+            fd = doppler_table(pix, blk["q_tx"], blk["q_rx"], blk["vel"], kd, height=height)
+            out += bp_alg2(pix, blk["q_tx"], blk["q_rx"], fd, blk["s"], w_j, a1, a2, height=height)
     return out
 
 

@@ -407,6 +407,97 @@ def test_point_target_with_height_focuses_only_with_it():
     assert amp[0.0] < 0.7 * amp[1.0]            # the planar reading loses more than 3 dB
 
 
+# ---------------------------------------------------------------------------
+# Continuous SAR: overlapping apertures of one chirp stream (Sec. V)
+# ---------------------------------------------------------------------------
+def _stream(n_blocks, S, CH=2, speed=3.0, seed=5, nb=150, yaw=0.0):
+    cfg = synth.SceneConfig("st", n_samples=64, n_chirps=n_blocks * S, n_tx=1, n_rx=CH, speed=speed,
+                            seed=seed, yaw_rate=yaw)
+    q_tx, q_rx, vel = synth._trajectory(cfg, speed)
+    rng = np.random.default_rng(seed + 1)
+    s = synth.random_spectrum(rng, (n_blocks * S, CH, nb)).astype(np.complex128)
+    blocks = [dict(q_tx=q_tx[j * S:(j + 1) * S], q_rx=q_rx[j * S:(j + 1) * S], vel=vel[j * S:(j + 1) * S],
+                   s=s[j * S:(j + 1) * S]) for j in range(n_blocks)]
+    return blocks, (q_tx, q_rx, vel, s)
+
+
+def test_sliding_exact_doppler_equals_whole_aperture():
+    """With per-term Doppler (Alg. 1) the aperture of sub-aperture b is Alg. 1
+    over its N = K S chirps with the window over N; before the stream has K
+    sub-apertures, the available chirps take the last positions of the window
+    (numpy's own Hann, not the oracle's)."""
+    K, S, nb = 3, 5, 6
+    blocks, (q_tx, q_rx, vel, s) = _stream(nb, S, yaw=0.05)
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    rng = np.random.default_rng(17)
+    pix = np.stack([rng.uniform(-3, 3, 30), rng.uniform(3, 8, 30)], -1)
+    N = K * S
+    for b in range(nb):
+        P = O.bp_sliding(pix, blocks, b, K, k["a1"], k["a2"], k["kd"], doppler="exact", f0=R["f0"],
+                         mu=k["mu"], df=k["df"])
+        lo = max(0, (b - K + 1) * S)
+        hi = (b + 1) * S
+        w = np.hanning(N)[N - (hi - lo):]
+        ref = O.bp_alg1(pix, q_tx[lo:hi], q_rx[lo:hi], vel[lo:hi], s[lo:hi], w, R["f0"], k["mu"], k["df"])
+        np.testing.assert_allclose(P, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_sliding_average_doppler_at_rest_equals_whole_aperture():
+    """At zero velocity every Doppler table is zero, so the aperture of the
+    averaged-Doppler form is Alg. 2 over its chirps; a rectangular window
+    makes it the plain sum of the sub-aperture images."""
+    K, S = 4, 3
+    blocks, (q_tx, q_rx, _, s) = _stream(6, S)
+    for blk in blocks:
+        blk["vel"] = np.zeros_like(blk["vel"])
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    rng = np.random.default_rng(18)
+    pix = np.stack([rng.uniform(-3, 3, 25), rng.uniform(3, 8, 25)], -1)
+    b = 5
+    P = O.bp_sliding(pix, blocks, b, K, k["a1"], k["a2"], k["kd"])
+    lo, hi = (b - K + 1) * S, (b + 1) * S
+    ref = O.bp_alg2(pix, q_tx[lo:hi], q_rx[lo:hi], np.zeros(25), s[lo:hi], np.hanning(K * S), k["a1"], k["a2"])
+    np.testing.assert_allclose(P, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    Pr = O.bp_sliding(pix, blocks, b, K, k["a1"], k["a2"], k["kd"], window_kind="rect")
+    parts = [O.bp_alg2(pix, blocks[j]["q_tx"], blocks[j]["q_rx"], np.zeros(25), blocks[j]["s"], np.ones(S),
+                       k["a1"], k["a2"]) for j in range(b - K + 1, b + 1)]
+    np.testing.assert_allclose(Pr, np.sum(parts, axis=0), rtol=0, atol=1e-12 * np.abs(Pr).max())
+
+
+def test_sliding_closed_form_gain_with_subaperture_doppler():
+    """P1 on a moving stream: a spectrum whose every sub-aperture j is matched
+    at p0 to the index a1 d_hyp + f_doppler_j(p0) of that sub-aperture's own
+    Doppler table focuses to N_ch times the sum of the window positions the
+    available chirps take (numpy's Hann)."""
+    K, S, CH, nbk = 4, 6, 2, 7
+    blocks, (q_tx, q_rx, vel, _) = _stream(nbk, S, CH=CH, speed=5.0, yaw=0.2)
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    p0 = np.array([[0.7, 5.5]])
+    kk = np.arange(200.0)
+    beta = 0.8 + 0.3j   # steep ramps: a Doppler table off by 0.01 bins shows
+    for j, blk in enumerate(blocks):
+        # velocities that differ from one sub-aperture to the next, so that
+        # every sub-aperture's Doppler table is its own
+        vx = (1.0, 7.0, 2.0, 8.0, 1.5, 6.0, 3.0)[j]
+        blk["vel"] = np.broadcast_to([vx, 0.1 * (-1) ** j], blk["vel"].shape).copy()
+        fdj = O.doppler_table(p0, blk["q_tx"], blk["q_rx"], blk["vel"], k["kd"])[0]
+        d0 = _dist(p0[0], blk["q_tx"]) + _dist(p0[0], blk["q_rx"])
+        f = k["a1"] * d0 + fdj
+        blk["s"] = np.exp(2j * np.pi * d0 / k["lam"])[:, :, None] * (1 + beta * (kk - f[:, :, None]))
+    N = K * S
+    for b in (1, 3, 6):
+        P = O.bp_sliding(p0, blocks, b, K, k["a1"], k["a2"], k["kd"])
+        n_avail = min(b + 1, K) * S
+        assert P[0] == pytest.approx(CH * np.hanning(N)[N - n_avail:].sum(), rel=1e-9)
+    # the whole-aperture table (Alg. 2 over the N chirps) does not match the ramps
+    lo, hi = 3 * S, 7 * S
+    vel_all = np.concatenate([blk["vel"] for blk in blocks[3:7]])
+    fd_ap = O.doppler_table(p0, q_tx[lo:hi], q_rx[lo:hi], vel_all, k["kd"])
+    s_all = np.concatenate([blk["s"] for blk in blocks[3:7]])
+    P_ap = O.bp_alg2(p0, q_tx[lo:hi], q_rx[lo:hi], fd_ap, s_all, np.hanning(N), k["a1"], k["a2"])
+    assert abs(P_ap[0] - CH * np.hanning(N).sum()) > 1e-3 * CH * np.hanning(N).sum()
+
+
 def test_doppler_average_error_below_100hz():
     """P9 (Sec. III-D): on a straight drive at parking speed the averaged table
     stays within 100 Hz of Alg. 1's per-chirp Doppler, the deviation obeys the
