@@ -28,8 +28,9 @@
  *     an error the thread-local message of rc_last_error() describes it.
  *   - A plan is used by one host thread at a time.  Streams are hipStream_t
  *     passed as void*; NULL means the default stream.
- *   - Distances are metres, frequencies Hz, times seconds.  Geometry is planar
- *     (x, y): the paper's 2-D distances.
+ *   - Distances are metres, frequencies Hz, times seconds.  Positions are
+ *     planar (x, y); distances are the paper's 2-D ones unless a frame gives
+ *     the antennas a height above the pixels' plane.
  */
 #ifndef RC_H_
 #define RC_H_
@@ -40,7 +41,7 @@
 extern "C" {
 #endif
 
-#define RC_ABI_VERSION 2
+#define RC_ABI_VERSION 3
 
 typedef enum rc_status {
   RC_OK = 0,
@@ -76,6 +77,24 @@ typedef enum rc_doppler_mode {
    * Single precision only (not with RC_PREC_FP32_SPLIT). */
   RC_DOPPLER_EXACT = 1
 } rc_doppler_mode;
+
+/* Continuous SAR (the paper's conclusion, Sec. V: a continuous measurement
+ * imaged as it arrives).  A sensor's chirp stream is cut into sub-apertures
+ * of S chirps, one rc_frame each; the image of sub-aperture b is the aperture
+ * of the last K sub-apertures (N = K S chirps, b - K + 1 .. b), weighted by
+ * the plan's chirp window over N positions (Sec. III-B); sub-apertures before
+ * the stream started hold no chirps.  With the averaged Doppler (Alg. 2) each
+ * sub-aperture's terms use that sub-aperture's own Doppler table (its mean
+ * positions and velocity, Sec. III-D).  Every chirp is back-projected once:
+ * the plan keeps, per sensor, the last sub-apertures' partial images (for the
+ * Hann window three of them: the plain sum and the sums weighted by the
+ * cosine and sine of the chirp's window phase, from which any window offset
+ * is one linear combination), and forms each aperture from them. */
+typedef enum rc_sliding {
+  RC_SLIDE_OFF = 0,    /* an independent aperture (default)                       */
+  RC_SLIDE_NEXT = 1,   /* the next sub-aperture of sensor_id's stream             */
+  RC_SLIDE_START = 2   /* the first sub-aperture of a new stream of sensor_id     */
+} rc_sliding;
 
 typedef enum rc_input_kind {
   RC_INPUT_RAW = 0,      /* data = beat signal complex64 [n_chirps][n_channels][n_samples] */
@@ -118,6 +137,13 @@ typedef struct rc_plan_desc {
   int64_t hbm_budget_bytes;     /* 0 = unlimited                                  */
   int32_t stage_timing;         /* nonzero: bracket every stage with timing events
                                    (read with rc_stage_times)                      */
+  /* continuous SAR (rc_sliding); sliding_sensors = 0 disables it.  The plan
+   * holds (K + depth - 1) partial images of n_pix_max pixels per sensor (three
+   * planes each with the Hann window, one with the rectangular one; the
+   * Kaiser window has no such decomposition and is refused) */
+  int32_t sliding_sensors;      /* sensors 0 .. sliding_sensors - 1                */
+  int32_t sliding_subapertures; /* K, sub-apertures per aperture, 1 .. 64          */
+  int32_t sliding_depth;        /* sub-apertures of one sensor in flight at once   */
 } rc_plan_desc;
 
 /* One radar frame (one synthetic aperture -> one image + detection list).
@@ -148,6 +174,16 @@ typedef struct rc_frame {
   double height;                /* antennas above the plane of the pixels, metres:
                                    distances become sqrt(|p - q|^2 + height^2);
                                    0 is the paper's planar geometry               */
+  rc_sliding sliding;           /* RC_SLIDE_NEXT / _START: this frame is the next
+                                   sub-aperture (n_chirps = S) of sensor_id's
+                                   stream; image_out and the detections are of the
+                                   aperture it completes.  Every sub-aperture of a
+                                   stream has the same n_chirps, n_channels,
+                                   lattice (n_rows, n_cols and the same pixels
+                                   pointer) and height; its doppler_out and
+                                   spectrum_out are the sub-aperture's own.  No
+                                   double-precision recheck (near-threshold cells
+                                   are flagged RC_DET_NEAR_THRESHOLD).            */
 } rc_frame;
 
 #define RC_DET_NEAR_THRESHOLD 1u  /* in the band, decided in single precision */
@@ -171,7 +207,11 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out);
 rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes);
 
 /* Enqueue n_frames frames on stream (Alg. 2 pipeline, steps 1-4 above).
- * Each frame takes a free slot.  Geometry is copied from the host arrays
+ * Each frame takes a free slot.  Sub-apertures of one stream are processed
+ * in the order given (within the batch and across calls, on any streams:
+ * the plan orders them with events); more than sliding_depth of one sensor
+ * in flight (unreleased) gives RC_ENOTREADY, RC_SLIDE_NEXT without a started
+ * stream or with sizes, lattice or height unlike the stream's RC_EINVAL.  Geometry is copied from the host arrays
  * before the call returns (through pinned staging), so they may be reused
  * at once; device inputs must stay valid until the frame completes.
  * Returns RC_ENOTREADY without enqueuing anything when fewer than n_frames

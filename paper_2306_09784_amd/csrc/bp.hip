@@ -30,6 +30,12 @@
 // A wave covers an 8 x 8 pixel block of the lattice so its gathers of one
 // (m, ch) row touch a handful of neighbouring bins.
 //
+// Sub-apertures of a continuous stream (SUMS = 3): the table carries no chirp
+// window; the lane keeps the plain sum of the terms and the sums weighted by
+// cos and sin of each chirp's window phase (per-row uniforms), from which the
+// runtime forms the windowed aperture: four extra multiply-adds per term
+// instead of back-projecting every chirp once per aperture it belongs to.
+//
 // Work distribution: one launch covers a batch of frames; its work items are
 // (frame, chirp block, 16 x 16 tile).  Workgroups are dispatched to the eight
 // XCDs round robin, so workgroup w runs on XCD k = w % 8 as its slot w / 8.
@@ -84,6 +90,7 @@ struct Stage {
   u32x4 e[U];
   float phi[U];
   float turn[U];
+  float wc[U], ws[U];  // SUMS == 3: the rows' window-phase weights (uniform)
 };
 
 // The terms of rows [row_begin, row_end) for one pixel, software-pipelined:
@@ -91,9 +98,9 @@ struct Stage {
 // multiply-accumulates of the current U rows, so their latency overlaps the
 // transcendentals.  U = min(CHG, 4) rows per stage; the TX leg is evaluated
 // once per group of CHG rows.
-template <int CHG, int FORM, bool CHECKED>
+template <int CHG, int FORM, bool CHECKED, int SUMS>
 __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int row_end, const float4 p,
-                                         const float fidx, float& out_re, float& out_im) {
+                                         const float fidx, float (&out_re)[SUMS], float (&out_im)[SUMS]) {
   constexpr bool EXACT = FORM == kBpExact;
   constexpr int U = CHG < 4 ? CHG : 4;
   constexpr int UPG = CHG / U;  // stages per TX group
@@ -102,10 +109,12 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   const float4* rq = (EXACT ? a.rowv : a.rowq) + row_begin;
   const float4* gq = (EXACT ? a.grpv : a.grpq) + row_begin / CHG;
   const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
+  const float2* rw = SUMS == 3 ? a.roww + row_begin : nullptr;
   const int n = row_end - row_begin;  // a multiple of CHG
   // per-pixel index base: plain f_doppler; split the index of the reference path
   const float fb = fidx;
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+  float rec = 0.f, imc = 0.f, res = 0.f, ims = 0.f;  // SUMS == 3: cos- and sin-weighted sums
   Leg<FORM> tx;
 
   auto tx_leg = [&](int r) {
@@ -120,6 +129,15 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
     float4 q[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) q[j] = make_float4(u[4 * j], u[4 * j + 1], u[4 * j + 2], u[4 * j + 3]);
+    if constexpr (SUMS == 3) {
+      typedef float wvec __attribute__((ext_vector_type(2 * U)));
+      const wvec wv = *reinterpret_cast<const wvec*>(rw + r);
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        st.wc[j] = wv[2 * j];
+        st.ws[j] = wv[2 * j + 1];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const Leg<FORM> rx = leg<FORM>(q[j], p);
@@ -164,7 +182,16 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       const float vr = fmaf(st.phi[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
       const float vi = fmaf(st.phi[j], __uint_as_float(st.e[j].w), __uint_as_float(st.e[j].y));
       // (cs - i sn) (vr + i vi)
-      if (((U == 1) ? par : j) & 1) {
+      if constexpr (SUMS == 3) {
+        const float tr = fmaf(cs, vr, sn * vi);
+        const float ti = fmaf(cs, vi, -(sn * vr));
+        re0 += tr;
+        im0 += ti;
+        rec = fmaf(st.wc[j], tr, rec);
+        imc = fmaf(st.wc[j], ti, imc);
+        res = fmaf(st.ws[j], tr, res);
+        ims = fmaf(st.ws[j], ti, ims);
+      } else if (((U == 1) ? par : j) & 1) {
         re1 = fmaf(cs, vr, re1);
         re1 = fmaf(sn, vi, re1);
         im1 = fmaf(cs, vi, im1);
@@ -198,8 +225,17 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   } else {
     consume(sa, 0);
   }
-  out_re = re0 + re1;
-  out_im = im0 + im1;
+  if constexpr (SUMS == 3) {
+    out_re[0] = re0;
+    out_im[0] = im0;
+    out_re[1] = rec;
+    out_im[1] = imc;
+    out_re[2] = res;
+    out_im[2] = ims;
+  } else {
+    out_re[0] = re0 + re1;
+    out_im[0] = im0 + im1;
+  }
 }
 
 // nearest and farthest distance from the pixel to an antenna in a box, with
@@ -217,7 +253,7 @@ __device__ __forceinline__ float box_max_dist(float px, float py, float lx, floa
   return sqrtf(dx * dx + dy * dy + h2);
 }
 
-template <int CHG, int FORM>
+template <int CHG, int FORM, int SUMS>
 __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   constexpr bool SPLIT = FORM == kBpSplit;
   constexpr bool EXACT = FORM == kBpExact;
@@ -275,13 +311,17 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   const int m1 = __builtin_amdgcn_readfirstlane((int)(((int64_t)(kb + 1) * a.n_chirps) / a.n_kb));
   const int row_begin = m0 * a.n_ch, row_end = m1 * a.n_ch;
 
-  float re, im;
+  float re[SUMS], im[SUMS];
   const float fb = SPLIT ? fi_p : fdp;
   if (__all(inside))
-    bp_terms<CHG, FORM, false>(a, row_begin, row_end, p, fb, re, im);
+    bp_terms<CHG, FORM, false, SUMS>(a, row_begin, row_end, p, fb, re, im);
   else
-    bp_terms<CHG, FORM, true>(a, row_begin, row_end, p, fb, re, im);
-  if (live) a.out[(int64_t)kb * a.n_rows * a.n_cols + idx] = make_float2(re, im);
+    bp_terms<CHG, FORM, true, SUMS>(a, row_begin, row_end, p, fb, re, im);
+  if (live) {
+    const int64_t n_pix = (int64_t)a.n_rows * a.n_cols;
+#pragma unroll
+    for (int k = 0; k < SUMS; ++k) a.out[((int64_t)kb * SUMS + k) * n_pix + idx] = make_float2(re[k], im[k]);
+  }
 }
 
 // Sum of the chirp-block partial images in block order.
@@ -299,14 +339,22 @@ __global__ __launch_bounds__(kThreads) void reduce_partials_kernel(ReduceBatch b
   }
 }
 
+template <int CHG, int SUMS>
+void launch_form(const BpBatch& b, dim3 grid, hipStream_t s) {
+  if (b.form == kBpSplit)
+    hipLaunchKernelGGL((bp_kernel<CHG, kBpSplit, SUMS>), grid, dim3(kThreads), 0, s, b);
+  else if (b.form == kBpExact)
+    hipLaunchKernelGGL((bp_kernel<CHG, kBpExact, SUMS>), grid, dim3(kThreads), 0, s, b);
+  else
+    hipLaunchKernelGGL((bp_kernel<CHG, kBpPlain, SUMS>), grid, dim3(kThreads), 0, s, b);
+}
+
 template <int CHG>
 void launch_chg(const BpBatch& b, dim3 grid, hipStream_t s) {
-  if (b.form == kBpSplit)
-    hipLaunchKernelGGL((bp_kernel<CHG, kBpSplit>), grid, dim3(kThreads), 0, s, b);
-  else if (b.form == kBpExact)
-    hipLaunchKernelGGL((bp_kernel<CHG, kBpExact>), grid, dim3(kThreads), 0, s, b);
+  if (b.sums == 3)
+    launch_form<CHG, 3>(b, grid, s);
   else
-    hipLaunchKernelGGL((bp_kernel<CHG, kBpPlain>), grid, dim3(kThreads), 0, s, b);
+    launch_form<CHG, 1>(b, grid, s);
 }
 
 }  // namespace
@@ -336,7 +384,7 @@ int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps) {
 
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
   if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_slots < 1 || b.chg < 1 || b.form < kBpPlain ||
-      b.form > kBpExact)
+      b.form > kBpExact || (b.sums != 1 && b.sums != 3))
     return hipErrorInvalidValue;
   int slots = 0;
   for (int i = 0; i < b.n_frames; ++i) {
@@ -345,6 +393,7 @@ hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
     bp_tiles(f.n_rows, f.n_cols, &tx, &nt);
     if (f.n_rows < 1 || f.n_cols < 1 || f.n_chirps < 1 || f.n_ch < 1 || f.n_bins < 2 || f.n_ch % b.chg != 0 ||
         (b.form == kBpExact && (!f.rowv || !f.grpv)) || (b.form != kBpExact && (!f.rowq || !f.grpq)) ||
+        (b.sums == 3 && (!f.roww || (reinterpret_cast<uintptr_t>(f.roww) & 31))) || !f.out ||
         f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.slot_base != slots ||
         f.chunk != (f.n_kb * nt + 7) / 8 ||
         (f.n_rows >= 8 && (f.n_rows + 15) / 16 > 0x7fffffff / 16) ||

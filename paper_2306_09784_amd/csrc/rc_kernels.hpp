@@ -118,7 +118,10 @@ struct BpFrame {
   // speed, so <P - q, kd v> / |P - q| is the Doppler index shift of one leg
   const float4* rowv;
   const float4* grpv;
-  float2* out;            // [n_kb][n_pix]: image (n_kb == 1) or partial images
+  // sub-aperture form (sums == 3): per row (cos, sin) of the chirp's window
+  // phase; the launch accumulates the plain sum and the two weighted sums
+  const float2* roww;
+  float2* out;            // [n_kb][sums][n_pix]: image(s) (n_kb == 1) or partial images
   int n_chirps, n_ch, n_bins;
   int n_rows, n_cols;
   int n_kb;               // chirp blocks
@@ -143,6 +146,7 @@ enum BpForm { kBpPlain = 0, kBpSplit = 1, kBpExact = 2 };
 
 struct BpBatch {
   int chg, form, n_frames, n_slots;  // n_slots: per-XCD slots (grid = 8 n_slots)
+  int sums;                          // 1, or 3 for sub-apertures under a Hann window
   BpFrame f[kBpMaxFrames];
 };
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s);
@@ -165,6 +169,27 @@ struct ReduceBatch {
   ReduceFrame f[kReduceMaxFrames];
 };
 hipError_t launch_reduce_partials(const ReduceBatch& b, hipStream_t s);
+
+// Aperture image of a continuous-SAR stream from the partial images of its
+// last n_blk sub-apertures, kept in a ring of n_ring slots of
+// [planes][n_pix] complex64 each (slot stride `stride` elements), oldest
+// first from slot `first`:
+//   out = sum_t (c0 S0_t + cc Sc_t + cs Ss_t)   (planes == 3)
+//   out = sum_t S0_t                            (planes == 1)
+struct CombineFrame {
+  const float2* ring;
+  int64_t stride;
+  int n_ring, first, n_blk, planes;
+  float c0, cc, cs;
+  float2* out;
+  int64_t n_pix;
+};
+constexpr int kCombineMaxFrames = 32;
+struct CombineBatch {
+  int n_frames;
+  CombineFrame f[kCombineMaxFrames];
+};
+hipError_t launch_combine(const CombineBatch& b, hipStream_t s);
 
 // 2-D CA-CFAR on |P|^2 (double) over the lattice.  mask holds one 64-bit word
 // per 64 columns of a row; det_cell receives the record of every detection at

@@ -1,7 +1,8 @@
 // C-ABI runtime of librc.so: plans, frame slots, host-side geometry
 // preparation and the stream-ordered launch sequence of the pipeline
 //   range compression -> Doppler table -> back-projection (Alg. 2) -> CA-CFAR
-// described in rc.h.
+// described in rc.h, and the per-sensor state of continuous SAR (sub-aperture
+// partial images in a ring, combined into each aperture).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -103,7 +104,32 @@ struct Slot {
   bool busy = false;
   int64_t frame_id = -1;
   int32_t n_rows = 0, n_cols = 0;
+  int32_t sensor = -1;        // continuous-SAR sensor of the frame in the slot, or -1
   float2* image_used = nullptr;
+};
+
+// A sensor's continuous-SAR stream: sub-aperture b's partial images live in
+// ring slot b % n_ring until n_ring newer sub-apertures have replaced them.
+struct Sensor {
+  bool started = false;
+  int64_t next = 0;    // sub-apertures of the current stream so far
+  int64_t stored = 0;  // sub-apertures ever stored (a new stream continues the ring)
+  int32_t n_chirps = 0, n_channels = 0, n_rows = 0, n_cols = 0;
+  const float* pixels = nullptr;
+  double height = 0;
+  hipEvent_t done = nullptr;  // recorded after the stream's last aperture was formed
+  hipStream_t stream = nullptr;
+  bool recorded = false;
+};
+
+// Where one sub-aperture's sums go and which aperture it completes.
+struct Slide {
+  int32_t sensor = -1;
+  int64_t block = 0;   // index of the sub-aperture in its stream
+  float2* dst = nullptr;
+  int ring_slot = 0;
+  int first_slot = 0;  // ring slot of the aperture's oldest sub-aperture
+  int n_blk = 1;       // sub-apertures of the aperture present in the stream
 };
 
 struct Plan {
@@ -114,7 +140,19 @@ struct Plan {
   int tw_log2 = 0;
   size_t geo_floats = 0;  // floats of the staging/rowgeo region
   std::vector<Slot> slots;
+  // continuous SAR: ring[sensor][n_ring][planes][n_pix_max]
+  std::vector<Sensor> sensors;
+  float2* ring = nullptr;
+  int n_ring = 0, planes = 0;
+  int64_t ring_stride = 0;  // complex values per ring slot
 };
+
+int sliding_planes(const rc_plan_desc& d) { return d.sar_window == RC_WIN_HANN ? 3 : 1; }
+int sliding_ring(const rc_plan_desc& d) { return d.sliding_subapertures + d.sliding_depth - 1; }
+size_t ring_bytes(const rc_plan_desc& d) {
+  if (d.sliding_sensors <= 0) return 0;
+  return (size_t)d.sliding_sensors * sliding_ring(d) * sliding_planes(d) * (size_t)d.n_pix_max * sizeof(float2);
+}
 
 struct SlotSizes {
   size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out, listed, rpower, spec64;
@@ -146,10 +184,13 @@ int64_t partial_capacity(const rc_plan_desc& d) {
 size_t recheck_floats(int64_t rows, int64_t n_chirps, int64_t n_samples) {
   return 4 * rows + 2 * n_chirps + 2 * n_chirps + 2 * n_samples;
 }
+// (a sub-aperture frame has no recheck; its per-row window-phase weights,
+// float2[rows], take the place of the recheck's region)
 size_t geo_floats(const rc_plan_desc& d) {
   const size_t rows = (size_t)d.n_chirps_max * d.n_channels_max;
   const size_t metres = d.max_rechecks > 0 ? recheck_floats(rows, d.n_chirps_max, d.n_samples_max) : 0;
-  return rows * 8 + metres + d.n_chirps_max + d.n_samples_max;
+  const size_t weights = d.sliding_sensors > 0 ? 2 * rows : 0;
+  return rows * 8 + std::max(metres, weights) + d.n_chirps_max + d.n_samples_max;
 }
 
 SlotSizes slot_sizes(const rc_plan_desc& d) {
@@ -204,6 +245,16 @@ rc_status validate_desc(const rc_plan_desc* d) {
   for (rc_window_kind k : {d->range_window, d->sar_window})
     if (k != RC_WIN_RECT && k != RC_WIN_HANN && k != RC_WIN_KAISER)
       return fail(RC_EINVAL, "unknown window kind %d", (int)k);
+  if (d->sliding_sensors < 0 || d->sliding_sensors > 4096)
+    return fail(RC_EINVAL, "sliding_sensors must be in [0, 4096]");
+  if (d->sliding_sensors > 0) {
+    if (d->sliding_subapertures < 1 || d->sliding_subapertures > 64)
+      return fail(RC_EINVAL, "sliding_subapertures must be in [1, 64]");
+    if (d->sliding_depth < 1 || d->sliding_depth > d->max_frames_in_flight)
+      return fail(RC_EINVAL, "sliding_depth must be in [1, max_frames_in_flight]");
+    if (d->sar_window == RC_WIN_KAISER)
+      return fail(RC_EINVAL, "continuous SAR needs the Hann or rectangular chirp window (a sum of cosines)");
+  }
   return RC_OK;
 }
 
@@ -220,9 +271,24 @@ void free_slot(Slot& s) {
 void free_plan(Plan* p) {
   if (!p) return;
   for (Slot& s : p->slots) free_slot(s);
+  for (Sensor& s : p->sensors)
+    if (s.done) (void)hipEventDestroy(s.done);
+  if (p->ring) (void)hipFree(p->ring);
   if (p->twiddle) (void)hipFree(p->twiddle);
   if (p->twiddle64) (void)hipFree(p->twiddle64);
   delete p;
+}
+
+// Chirp blocks of a frame's back-projection; a sub-aperture's partial images
+// have `planes` planes each and must fit the slot's partial buffer.
+int frame_chirp_blocks(const Plan* p, const rc_frame& f) {
+  int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps);
+  if (f.sliding != RC_SLIDE_OFF && n_kb > 1) {
+    const int64_t per = (int64_t)p->planes * f.n_rows * f.n_cols;
+    const int64_t fit = partial_capacity(p->d) / per;
+    if (fit < n_kb) n_kb = fit < 2 ? 1 : (int)fit;
+  }
+  return n_kb;
 }
 
 Slot* find_slot(Plan* p, int64_t id) {
@@ -254,8 +320,17 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
   for (int64_t i = 0; i < 2 * (int64_t)f.n_chirps; ++i)
     if (!std::isfinite(f.vel[i]))
       return fail(RC_EINVAL, "frame %lld: non-finite velocity", (long long)f.frame_id);
-  const int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps);
-  if (n_kb > 1 && (int64_t)n_kb * f.n_rows * f.n_cols > partial_capacity(d))
+  if (f.sliding != RC_SLIDE_OFF) {
+    if (f.sliding != RC_SLIDE_NEXT && f.sliding != RC_SLIDE_START)
+      return fail(RC_EINVAL, "frame %lld: unknown sliding mode %d", (long long)f.frame_id, (int)f.sliding);
+    if (d.sliding_sensors <= 0)
+      return fail(RC_EINVAL, "frame %lld: the plan has no continuous-SAR sensors", (long long)f.frame_id);
+    if (f.sensor_id < 0 || f.sensor_id >= d.sliding_sensors)
+      return fail(RC_EINVAL, "frame %lld: sensor %d outside [0, %d)", (long long)f.frame_id, f.sensor_id, d.sliding_sensors);
+  }
+  const int n_kb = frame_chirp_blocks(p, f);
+  const int planes = f.sliding != RC_SLIDE_OFF ? p->planes : 1;
+  if (n_kb > 1 && (int64_t)n_kb * planes * f.n_rows * f.n_cols > partial_capacity(d))
     return fail(RC_EINVAL, "frame %lld: %d chirp blocks exceed the partial-image buffer", (long long)f.frame_id, n_kb);
   if (f.input_kind == RC_INPUT_RAW) {
     if (f.n_samples < 1 || f.n_samples > d.n_samples_max)
@@ -301,13 +376,16 @@ struct Prepared {
   rc::TableArgs ta{};
   rc::BpFrame bf{};
   int chg = 1;
+  int sums = 1;  // 3: a continuous-SAR sub-aperture under the Hann window
 };
 
 // Host part of a frame: geometry in local units through pinned staging (and,
 // with the recheck on, the double-precision spectrum), and the argument
 // blocks of its range compression, pixel tables and back-projection, which
-// the batch launches for many frames at once.
-rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Prepared* out) {
+// the batch launches for many frames at once.  A continuous-SAR sub-aperture
+// (sl != nullptr) has an unwindowed table, per-row window-phase weights and
+// writes its sums to its ring slot.
+rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hipStream_t st, Prepared* out) {
   const rc_plan_desc& d = p->d;
   const double c = d.radar.c > 0 ? d.radar.c : 299792458.0;
   const double mu = d.radar.bandwidth / d.radar.t_chirp;
@@ -363,9 +441,10 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
   }
   vx /= f.n_chirps;
   vy /= f.n_chirps;
-  const bool recheck = d.max_rechecks > 0;
+  const bool recheck = d.max_rechecks > 0 && !sl;
   const int n_s = f.input_kind == RC_INPUT_RAW ? f.n_samples : 0;
-  const int64_t metres = recheck ? (int64_t)recheck_floats(rows, f.n_chirps, n_s) : 0;
+  // the recheck's geometry or a sub-aperture's window-phase weights
+  const int64_t metres = recheck ? (int64_t)recheck_floats(rows, f.n_chirps, n_s) : sl ? 2 * rows : 0;
   float4* geo_m = rowq + 2 * rows;
   float2* vel_m = reinterpret_cast<float2*>(geo_m + rows);
   double* w_sar64 = reinterpret_cast<double*>(vel_m + f.n_chirps);
@@ -377,8 +456,24 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
     make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar64);
     make_window(d.range_window, d.range_kaiser_beta, n_s, w_range64);
   }
+  if (sl) {
+    // chirp m of sub-aperture b is chirp b S + m of the stream; its window
+    // phase is 2 pi ((b S + m) mod (N - 1)) / (N - 1), N = K S (exact in integers)
+    float2* roww = reinterpret_cast<float2*>(geo_m);
+    const int64_t period = (int64_t)d.sliding_subapertures * f.n_chirps - 1;
+    for (int m = 0; m < f.n_chirps; ++m) {
+      float2 w = make_float2(1.f, 0.f);
+      if (period > 0) {
+        const double th = 2.0 * kPi * (double)((sl->block * f.n_chirps + m) % period) / (double)period;
+        w = make_float2((float)std::cos(th), (float)std::sin(th));
+      }
+      for (int c = 0; c < f.n_channels; ++c) roww[(int64_t)m * f.n_channels + c] = w;
+    }
+  }
   float* w_sar = g + 8 * rows + metres;
-  make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
+  // a sub-aperture's table is unwindowed: the window enters when the
+  // aperture is formed from the sums
+  make_window(sl ? RC_WIN_RECT : d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
   float* w_range = w_sar + f.n_chirps;
   make_window(d.range_window, d.range_kaiser_beta, n_s, w_range);
   const size_t geo_bytes = (size_t)(8 * rows + metres + f.n_chirps + n_s) * sizeof(float);
@@ -452,7 +547,8 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
 
   // back-projection descriptor (Alg. 2), launched batch-wide by the caller
   float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
-  const int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps);
+  const int n_kb = frame_chirp_blocks(p, f);
+  const int planes = sl ? p->planes : 1;
   rc::BpFrame& ba = out->bf;
   ba = rc::BpFrame{};
   ba.pixc = s.pixc;
@@ -464,7 +560,8 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
   ba.grpv = exact ? d_grpq : nullptr;
   // each leg's Doppler index shift is at most kd |v|
   ba.f_slack = exact ? (float)(2.0 * kd * vmax * (1.0 + 1e-6)) : 0.f;
-  ba.out = n_kb > 1 ? s.partials : img;
+  ba.roww = sl && planes == 3 ? reinterpret_cast<const float2*>(s.rowgeo + 2 * rows) : nullptr;
+  ba.out = n_kb > 1 ? s.partials : sl ? sl->dst : img;
   ba.n_chirps = f.n_chirps;
   ba.n_ch = f.n_channels;
   ba.n_bins = f.n_bins;
@@ -479,7 +576,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
   // ulps of n_bins; the margin keeps such waves on the range-tested path
   ba.f_margin = (float)(1e-3 + 64.0 * f.n_bins * std::ldexp(1.0, -24));
   ba.h2 = (float)(f.height * inv_lam * f.height * inv_lam);
-  if (n_kb > 1 && (int64_t)n_kb * n_pix > s.partial_cap)
+  if (n_kb > 1 && (int64_t)n_kb * planes * n_pix > s.partial_cap)
     return fail(RC_EINVAL, "frame %lld: %d chirp blocks of %lld pixels exceed the slot's partial buffer",
                 (long long)f.frame_id, n_kb, (long long)n_pix);
   // geometry of the double-precision recheck (metres, Alg. 2 or Alg. 1)
@@ -504,10 +601,12 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, hipStream_t st, Pre
     rk.height = f.height;
   }
   out->chg = chg;
+  out->sums = planes;
   s.busy = true;
   s.frame_id = f.frame_id;
   s.n_rows = f.n_rows;
   s.n_cols = f.n_cols;
+  s.sensor = sl ? sl->sensor : -1;
   s.image_used = img;
   return RC_OK;
 }
@@ -521,22 +620,25 @@ rc_status finish_batch(Plan* p, const std::vector<Slot*>& slot, const rc_frame* 
   const int h = d.cfar_guard + d.cfar_train;
   const int n_train = (2 * h + 1) * (2 * h + 1) - (2 * d.cfar_guard + 1) * (2 * d.cfar_guard + 1);
   const double alpha = n_train * (std::pow(d.cfar_pfa, -1.0 / n_train) - 1.0);
-  const bool recheck = d.max_rechecks > 0;
+  // continuous-SAR apertures are not rechecked (their sub-apertures' spectra
+  // are gone by the time a cell is listed)
+  auto rechecked = [&](int i) { return d.max_rechecks > 0 && frames[i].sliding == RC_SLIDE_OFF; };
   auto wpr = [&](int i) { return (frames[i].n_cols + 63) / 64; };
-  if (recheck)
-    for (int i = 0; i < n; ++i) RC_HIP(rc::launch_clear_count(slot[i]->n_listed, st));
+  for (int i = 0; i < n; ++i)
+    if (rechecked(i)) RC_HIP(rc::launch_clear_count(slot[i]->n_listed, st));
   for (int i0 = 0; i0 < n; i0 += rc::CfarMulti::kMax) {
     rc::CfarMulti m;
     for (int i = i0; i < n && m.n_frames < rc::CfarMulti::kMax; ++i) {
       Slot& s = *slot[i];
       m.f[m.n_frames++] = rc::CfarArgs{s.image_used, frames[i].n_rows, frames[i].n_cols, d.cfar_guard,
                                        d.cfar_train, alpha / n_train, d.cfar_margin_rel, s.mask, wpr(i),
-                                       s.det_cell, s.listed, s.n_listed, recheck ? d.max_rechecks : 0};
+                                       s.det_cell, s.listed, s.n_listed, rechecked(i) ? d.max_rechecks : 0};
     }
     RC_HIP(rc::launch_cfar(m, st));
   }
-  if (recheck) {
+  {
     for (int i = 0; i < n; ++i) {
+      if (!rechecked(i)) continue;
       Slot& s = *slot[i];
       rc::RecheckArgs rk = s.rk;
       rk.listed = s.listed;
@@ -596,7 +698,7 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
   const size_t per_slot = sz.total();
   const size_t tw_bytes = (size_t)desc->n_fft_max * sizeof(float2);
   const size_t tw64_bytes = desc->max_rechecks > 0 ? (size_t)desc->n_fft_max / 2 * sizeof(double2) : 0;
-  const size_t need = per_slot * desc->max_frames_in_flight + tw_bytes + tw64_bytes;
+  const size_t need = per_slot * desc->max_frames_in_flight + tw_bytes + tw64_bytes + ring_bytes(*desc);
   if (desc->hbm_budget_bytes > 0 && need > (size_t)desc->hbm_budget_bytes)
     return fail(RC_ENOMEM, "plan needs %zu bytes of device memory, budget is %lld", need,
                 (long long)desc->hbm_budget_bytes);
@@ -632,6 +734,24 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     if (e != hipSuccess) {
       free_plan(p);
       return fail(e == hipErrorOutOfMemory ? RC_ENOMEM : RC_EHIP, "twiddle table: %s", hipGetErrorString(e));
+    }
+  }
+  if (desc->sliding_sensors > 0) {
+    p->n_ring = sliding_ring(*desc);
+    p->planes = sliding_planes(*desc);
+    p->ring_stride = (int64_t)p->planes * desc->n_pix_max;
+    e = hipMalloc(&p->ring, ring_bytes(*desc));
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(RC_ENOMEM, "continuous-SAR ring of %zu bytes: %s", ring_bytes(*desc), hipGetErrorString(e));
+    }
+    p->sensors.resize(desc->sliding_sensors);
+    for (Sensor& sn : p->sensors) {
+      e = hipEventCreateWithFlags(&sn.done, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        free_plan(p);
+        return fail(RC_EHIP, "event creation failed: %s", hipGetErrorString(e));
+      }
     }
   }
   p->slots.resize(desc->max_frames_in_flight);
@@ -700,12 +820,55 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
         return fail(RC_EINVAL, "frame id %lld repeated in the batch", (long long)frames[i].frame_id);
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // continuous SAR: each sub-aperture's place in its stream, in batch order,
+  // on a copy of the sensors' state that the batch commits when it succeeds
+  std::vector<Slide> slide(n_frames);
+  std::vector<Sensor> sensors = p->sensors;
+  {
+    std::vector<int> in_flight(p->sensors.size(), 0);
+    for (const Slot& s : p->slots)
+      if (s.busy && s.sensor >= 0) ++in_flight[s.sensor];
+    for (int i = 0; i < n_frames; ++i) {
+      const rc_frame& f = frames[i];
+      if (f.sliding == RC_SLIDE_OFF) continue;
+      Sensor& sn = sensors[f.sensor_id];
+      if (f.sliding == RC_SLIDE_START) {
+        sn.started = true;
+        sn.next = 0;
+        sn.n_chirps = f.n_chirps;
+        sn.n_channels = f.n_channels;
+        sn.n_rows = f.n_rows;
+        sn.n_cols = f.n_cols;
+        sn.pixels = f.pixels;
+        sn.height = f.height;
+      } else if (!sn.started) {
+        return fail(RC_EINVAL, "frame %lld: sensor %d has no stream (start one with RC_SLIDE_START)",
+                    (long long)f.frame_id, f.sensor_id);
+      } else if (f.n_chirps != sn.n_chirps || f.n_channels != sn.n_channels || f.n_rows != sn.n_rows ||
+                 f.n_cols != sn.n_cols || f.pixels != sn.pixels || f.height != sn.height) {
+        return fail(RC_EINVAL, "frame %lld: sub-aperture of sensor %d unlike its stream (chirps, channels, "
+                    "lattice, pixels and height must stay)", (long long)f.frame_id, f.sensor_id);
+      }
+      if (++in_flight[f.sensor_id] > p->d.sliding_depth)
+        return fail(RC_ENOTREADY, "frame %lld: more than %d sub-apertures of sensor %d in flight",
+                    (long long)f.frame_id, p->d.sliding_depth, f.sensor_id);
+      Slide& sl = slide[i];
+      sl.sensor = f.sensor_id;
+      sl.block = sn.next;
+      sl.ring_slot = (int)(sn.stored % p->n_ring);
+      sl.n_blk = (int)std::min<int64_t>(sn.next + 1, p->d.sliding_subapertures);
+      sl.first_slot = (int)((sn.stored - (sl.n_blk - 1)) % p->n_ring);
+      sl.dst = p->ring + ((int64_t)f.sensor_id * p->n_ring + sl.ring_slot) * p->ring_stride;
+      ++sn.next;
+      ++sn.stored;
+    }
+  }
   std::vector<Slot*> slot(n_frames, nullptr);
   std::vector<Prepared> prep(n_frames);
-  auto undo = [&](rc_status r) {  // a failed batch leaves no slot busy
+  auto undo = [&](rc_status r) {  // a failed batch leaves no slot busy and no stream advanced
     (void)hipStreamSynchronize(st);
     for (Slot* q : slot)
-      if (q) { q->busy = false; q->frame_id = -1; }
+      if (q) { q->busy = false; q->frame_id = -1; q->sensor = -1; }
     return r;
   };
 #define RC_BATCH(call)                                                                  \
@@ -715,11 +878,19 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
       return undo(fail(RC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)));        \
   } while (0)
   const bool timed = p->d.stage_timing != 0;
+  // sub-apertures whose stream's previous aperture was formed on another
+  // stream wait for it (their aperture reads its partial images)
+  for (size_t k = 0; k < sensors.size(); ++k) {
+    bool used = false;
+    for (int i = 0; i < n_frames && !used; ++i) used = slide[i].sensor == (int)k;
+    if (used && p->sensors[k].recorded && p->sensors[k].stream != st)
+      RC_BATCH(hipStreamWaitEvent(st, p->sensors[k].done, 0));
+  }
   // host part of every frame: geometry upload, argument blocks
   for (int i = 0; i < n_frames; ++i) {
     for (Slot& c : p->slots)
       if (!c.busy) { slot[i] = &c; break; }
-    rc_status r = prepare_frame(p, *slot[i], frames[i], st, &prep[i]);
+    rc_status r = prepare_frame(p, *slot[i], frames[i], slide[i].sensor >= 0 ? &slide[i] : nullptr, st, &prep[i]);
     if (r != RC_OK) return undo(r);
   }
   // 1: range compression, one launch per DFT length and 32 frames
@@ -776,11 +947,12 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     if (done[i]) continue;
     rc::BpBatch b{};
     b.chg = prep[i].chg;
+    b.sums = prep[i].sums;
     b.form = p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
              : p->d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
     for (int oj = oi; oj < n_frames && b.n_frames < rc::kBpMaxFrames; ++oj) {
       const int j = order[oj];
-      if (done[j] || prep[j].chg != prep[i].chg) continue;
+      if (done[j] || prep[j].chg != prep[i].chg || prep[j].sums != prep[i].sums) continue;
       rc::BpFrame fj = prep[j].bf;
       fj.chunk = (fj.n_kb * fj.n_tiles + 7) / 8;
       fj.slot_base = b.n_slots;
@@ -793,20 +965,66 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   rc::ReduceBatch rb{};
   for (int i = 0; i < n_frames; ++i) {
     if (prep[i].bf.n_kb == 1) continue;
-    rb.f[rb.n_frames++] = rc::ReduceFrame{prep[i].bf.out, slot[i]->image_used,
-                                          (int64_t)frames[i].n_rows * frames[i].n_cols, prep[i].bf.n_kb};
+    // a sub-aperture's [planes][n_pix] sums reduce like one image of planes n_pix pixels
+    float2* dst = slide[i].sensor >= 0 ? slide[i].dst : slot[i]->image_used;
+    rb.f[rb.n_frames++] = rc::ReduceFrame{prep[i].bf.out, dst,
+                                          (int64_t)prep[i].sums * frames[i].n_rows * frames[i].n_cols,
+                                          prep[i].bf.n_kb};
     if (rb.n_frames == rc::kReduceMaxFrames) {
       RC_BATCH(rc::launch_reduce_partials(rb, st));
       rb.n_frames = 0;
     }
   }
   if (rb.n_frames) RC_BATCH(rc::launch_reduce_partials(rb, st));
+  // continuous SAR: each sub-aperture's aperture from the ring.  The window
+  // over the aperture's N = K S chirps starts at chirp a = (b - K + 1) S of the
+  // stream: w(m) = 1/2 - 1/2 cos(theta_m - phi), phi = 2 pi (a mod (N - 1)) / (N - 1)
+  rc::CombineBatch cb{};
+  for (int i = 0; i < n_frames; ++i) {
+    const Slide& sl = slide[i];
+    if (sl.sensor < 0) continue;
+    rc::CombineFrame& c = cb.f[cb.n_frames++];
+    c = rc::CombineFrame{};
+    c.ring = p->ring + (int64_t)sl.sensor * p->n_ring * p->ring_stride;
+    c.stride = p->ring_stride;
+    c.n_ring = p->n_ring;
+    c.first = sl.first_slot;
+    c.n_blk = sl.n_blk;
+    c.planes = p->planes;
+    c.c0 = 1.f;
+    if (p->planes == 3) {
+      const int64_t period = (int64_t)p->d.sliding_subapertures * frames[i].n_chirps - 1;
+      if (period > 0) {
+        const int64_t a = (sl.block - p->d.sliding_subapertures + 1) * frames[i].n_chirps;
+        const double phi = 2.0 * kPi * (double)(((a % period) + period) % period) / (double)period;
+        c.c0 = 0.5f;
+        c.cc = (float)(-0.5 * std::cos(phi));
+        c.cs = (float)(-0.5 * std::sin(phi));
+      }
+    }
+    c.out = slot[i]->image_used;
+    c.n_pix = (int64_t)frames[i].n_rows * frames[i].n_cols;
+    if (cb.n_frames == rc::kCombineMaxFrames) {
+      RC_BATCH(rc::launch_combine(cb, st));
+      cb.n_frames = 0;
+    }
+  }
+  if (cb.n_frames) RC_BATCH(rc::launch_combine(cb, st));
+  for (size_t k = 0; k < sensors.size(); ++k) {
+    bool used = false;
+    for (int i = 0; i < n_frames && !used; ++i) used = slide[i].sensor == (int)k;
+    if (!used) continue;
+    RC_BATCH(hipEventRecord(sensors[k].done, st));
+    sensors[k].stream = st;
+    sensors[k].recorded = true;
+  }
   if (timed)
     for (Slot* q : slot) RC_BATCH(hipEventRecord(q->stage_ev[3], st));
 #undef RC_BATCH
   // 4: detection and read-back
   rc_status r = finish_batch(p, slot, frames, n_frames, st);
   if (r != RC_OK) return undo(r);
+  p->sensors = sensors;
   return RC_OK;
 }
 
@@ -874,6 +1092,7 @@ rc_status rc_frame_release(void* plan, int64_t frame_id) {
   RC_HIP(hipEventSynchronize(s->done));
   s->busy = false;
   s->frame_id = -1;
+  s->sensor = -1;
   return RC_OK;
 }
 

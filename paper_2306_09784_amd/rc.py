@@ -16,7 +16,7 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librc.so")
 
-RC_ABI_VERSION = 2
+RC_ABI_VERSION = 3
 
 # rc_status
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_ETRUNC, RC_EHIP, RC_ENOTREADY, RC_ENOTFOUND = range(7)
@@ -31,6 +31,8 @@ RC_PREC_FP32, RC_PREC_FP32_SPLIT = 0, 1
 RC_DOPPLER_AVERAGE, RC_DOPPLER_EXACT = 0, 1
 # rc_input_kind
 RC_INPUT_RAW, RC_INPUT_SPECTRUM = 0, 1
+# rc_sliding (continuous SAR: sub-apertures of a sensor's chirp stream)
+RC_SLIDE_OFF, RC_SLIDE_NEXT, RC_SLIDE_START = 0, 1, 2
 RC_DET_NEAR_THRESHOLD = 1
 RC_DET_RECHECKED = 2
 
@@ -65,6 +67,9 @@ class rc_plan_desc(C.Structure):
         ("max_rechecks", C.c_int32),
         ("hbm_budget_bytes", C.c_int64),
         ("stage_timing", C.c_int32),
+        ("sliding_sensors", C.c_int32),
+        ("sliding_subapertures", C.c_int32),
+        ("sliding_depth", C.c_int32),
     ]
 
 
@@ -90,6 +95,7 @@ class rc_frame(C.Structure):
         ("doppler_out", C.c_void_p),
         ("spectrum_out", C.c_void_p),
         ("height", C.c_double),
+        ("sliding", C.c_int),
     ]
 
 
@@ -225,6 +231,9 @@ class PlanConfig:
     max_rechecks: int = 0
     hbm_budget_bytes: int = 0
     stage_timing: bool = False
+    sliding_sensors: int = 0
+    sliding_subapertures: int = 1
+    sliding_depth: int = 1
 
     def desc(self) -> rc_plan_desc:
         r = self.radar
@@ -234,7 +243,8 @@ class PlanConfig:
             self.n_channels_max, self.n_pix_max, self.max_frames_in_flight, self.max_detections,
             WINDOWS[self.range_window], self.range_kaiser_beta, WINDOWS[self.sar_window],
             self.sar_kaiser_beta, self.precision, self.doppler, self.cfar_guard, self.cfar_train, self.cfar_pfa,
-            self.cfar_margin_rel, self.max_rechecks, self.hbm_budget_bytes, int(self.stage_timing))
+            self.cfar_margin_rel, self.max_rechecks, self.hbm_budget_bytes, int(self.stage_timing),
+            self.sliding_sensors, self.sliding_subapertures, self.sliding_depth)
 
 
 def slot_bytes(cfg: PlanConfig) -> int:
@@ -293,7 +303,8 @@ class Plan:
     def make_frame(frame_id: int, *, data, q_tx: np.ndarray, q_rx: np.ndarray, vel: np.ndarray,
                    pixels, n_rows: int, n_cols: int, n_bins: int, n_fft: int, fs: float,
                    n_samples: int = 0, input_kind: int = RC_INPUT_RAW, image_out=None,
-                   doppler_out=None, spectrum_out=None, sensor_id: int = 0, height: float = 0.0) -> rc_frame:
+                   doppler_out=None, spectrum_out=None, sensor_id: int = 0, height: float = 0.0,
+                   sliding: int = RC_SLIDE_OFF) -> rc_frame:
         """Builds an rc_frame.  q_tx, q_rx, vel must be C-contiguous float32
         host arrays that stay alive until rc_process_batch returns."""
         for a in (q_tx, q_rx, vel):
@@ -305,7 +316,7 @@ class Plan:
         return rc_frame(frame_id, sensor_id, n_samples, n_fft, n_bins, M, CH, fs, input_kind,
                         _ptr(data), q_tx.ctypes.data, q_rx.ctypes.data, vel.ctypes.data,
                         _ptr(pixels), n_rows, n_cols, _ptr(image_out), _ptr(doppler_out),
-                        _ptr(spectrum_out), float(height))
+                        _ptr(spectrum_out), float(height), int(sliding))
 
     def process(self, frames, stream=None) -> int:
         arr = (rc_frame * len(frames))(*frames)

@@ -54,8 +54,9 @@ int main(void) {
   P(rc_plan_desc, radar) P(rc_plan_desc, n_pix_max) P(rc_plan_desc, range_window)
   P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision) P(rc_plan_desc, doppler)
   P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, max_rechecks) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
+  P(rc_plan_desc, sliding_sensors) P(rc_plan_desc, sliding_subapertures) P(rc_plan_desc, sliding_depth)
   P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
-  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out) P(rc_frame, height)
+  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out) P(rc_frame, height) P(rc_frame, sliding)
   P(rc_detection, threshold) P(rc_detection, flags)
   return 0;
 }
@@ -109,6 +110,27 @@ def test_descriptor_validation(rc):
     h = C.c_void_p()
     assert rc.lib.rc_plan_create(C.byref(d), C.byref(h)) == rc.RC_EINVAL
     assert "abi_version" in rc.last_error()
+
+
+def test_sliding_descriptor_validation(rc):
+    """Continuous SAR: K in [1, 64], depth in [1, max_frames_in_flight], and a
+    chirp window that is a sum of cosines (Hann or rectangular); the ring of
+    (K + depth - 1) partial images per sensor counts against the HBM budget."""
+    ok = dict(sliding_sensors=2, sliding_subapertures=4, sliding_depth=2, max_frames_in_flight=4)
+    rc.slot_bytes(_cfg(rc, **ok))
+    rc.slot_bytes(_cfg(rc, **ok, sar_window="rect"))
+    for kw in (dict(sliding_subapertures=0), dict(sliding_subapertures=65), dict(sliding_depth=0),
+               dict(sliding_depth=5), dict(sar_window="kaiser"), dict(sliding_sensors=-1)):
+        with pytest.raises(rc.RcError) as ei:
+            rc.slot_bytes(_cfg(rc, **{**ok, **kw}))
+        assert ei.value.status == rc.RC_EINVAL, kw
+    # the Kaiser window is fine without continuous SAR
+    rc.slot_bytes(_cfg(rc, sar_window="kaiser"))
+    # 2 sensors x 5 ring slots x 3 planes x 65536 pixels x 8 B = 15.7 MB over a 15 MB budget
+    slots = rc.slot_bytes(_cfg(rc, **ok)) * 4
+    with pytest.raises(rc.RcError) as ei:
+        rc.Plan(_cfg(rc, **ok, hbm_budget_bytes=slots + (1 << 20)))
+    assert ei.value.status == rc.RC_ENOMEM and "budget" in rc.last_error()
 
 
 def test_budget_rejection_before_any_device_call(rc):
