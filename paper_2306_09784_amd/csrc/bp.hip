@@ -32,9 +32,11 @@
 //
 // Sub-apertures of a continuous stream (SUMS = 3): the table carries no chirp
 // window; the lane keeps the plain sum of the terms and the sums weighted by
-// cos and sin of each chirp's window phase (per-row uniforms), from which the
-// runtime forms the windowed aperture: four extra multiply-adds per term
-// instead of back-projecting every chirp once per aperture it belongs to.
+// cos and sin of each chirp's window phase, from which the runtime forms the
+// windowed aperture, instead of back-projecting every chirp once per
+// aperture it belongs to.  All channels of a chirp share its weights, so the
+// terms of a chirp accumulate as usual and their sum enters the three sums
+// once per chirp (a dozen instructions per chirp and pixel).
 //
 // Work distribution: one launch covers a batch of frames; its work items are
 // (frame, chirp block, 16 x 16 tile).  Workgroups are dispatched to the eight
@@ -90,7 +92,6 @@ struct Stage {
   u32x4 e[U];
   float phi[U];
   float turn[U];
-  float wc[U], ws[U];  // SUMS == 3: the rows' window-phase weights (uniform)
 };
 
 // The terms of rows [row_begin, row_end) for one pixel, software-pipelined:
@@ -109,12 +110,17 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   const float4* rq = (EXACT ? a.rowv : a.rowq) + row_begin;
   const float4* gq = (EXACT ? a.grpv : a.grpq) + row_begin / CHG;
   const float4* tab = a.pairs + (size_t)row_begin * a.n_bins;
-  const float2* rw = SUMS == 3 ? a.roww + row_begin : nullptr;
+  // SUMS == 3: the chirps' window-phase weights (cos, sin), one per chirp
+  const float2* wp = SUMS == 3 ? a.roww + row_begin / a.n_ch : nullptr;
+  const float2* wend = SUMS == 3 ? a.roww + row_end / a.n_ch : nullptr;
   const int n = row_end - row_begin;  // a multiple of CHG
   // per-pixel index base: plain f_doppler; split the index of the reference path
   const float fb = fidx;
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  float rec = 0.f, imc = 0.f, res = 0.f, ims = 0.f;  // SUMS == 3: cos- and sin-weighted sums
+  // SUMS == 3: the plain, cos- and sin-weighted sums over the chirps done
+  float s0r = 0.f, s0i = 0.f, scr = 0.f, sci = 0.f, ssr = 0.f, ssi = 0.f;
+  float2 wcur = SUMS == 3 ? wp[0] : make_float2(0.f, 0.f);
+  int chirp_rows = 0;  // rows of the current chirp consumed (wave-uniform)
   Leg<FORM> tx;
 
   auto tx_leg = [&](int r) {
@@ -129,15 +135,6 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
     float4 q[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) q[j] = make_float4(u[4 * j], u[4 * j + 1], u[4 * j + 2], u[4 * j + 3]);
-    if constexpr (SUMS == 3) {
-      typedef float wvec __attribute__((ext_vector_type(2 * U)));
-      const wvec wv = *reinterpret_cast<const wvec*>(rw + r);
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        st.wc[j] = wv[2 * j];
-        st.ws[j] = wv[2 * j + 1];
-      }
-    }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const Leg<FORM> rx = leg<FORM>(q[j], p);
@@ -182,16 +179,7 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       const float vr = fmaf(st.phi[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
       const float vi = fmaf(st.phi[j], __uint_as_float(st.e[j].w), __uint_as_float(st.e[j].y));
       // (cs - i sn) (vr + i vi)
-      if constexpr (SUMS == 3) {
-        const float tr = fmaf(cs, vr, sn * vi);
-        const float ti = fmaf(cs, vi, -(sn * vr));
-        re0 += tr;
-        im0 += ti;
-        rec = fmaf(st.wc[j], tr, rec);
-        imc = fmaf(st.wc[j], ti, imc);
-        res = fmaf(st.ws[j], tr, res);
-        ims = fmaf(st.ws[j], ti, ims);
-      } else if (((U == 1) ? par : j) & 1) {
+      if (((U == 1) ? par : j) & 1) {
         re1 = fmaf(cs, vr, re1);
         re1 = fmaf(sn, vi, re1);
         im1 = fmaf(cs, vi, im1);
@@ -201,6 +189,23 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
         re0 = fmaf(sn, vi, re0);
         im0 = fmaf(cs, vi, im0);
         im0 = fmaf(-sn, vr, im0);
+      }
+    }
+    if constexpr (SUMS == 3) {
+      // U divides the channels of a chirp: at the end of a chirp its sum joins
+      // the three sums with the chirp's weights and the accumulators restart
+      chirp_rows += U;
+      if (chirp_rows == a.n_ch) {
+        chirp_rows = 0;
+        const float tr = re0 + re1, ti = im0 + im1;
+        s0r += tr;
+        s0i += ti;
+        scr = fmaf(wcur.x, tr, scr);
+        sci = fmaf(wcur.x, ti, sci);
+        ssr = fmaf(wcur.y, tr, ssr);
+        ssi = fmaf(wcur.y, ti, ssi);
+        re0 = re1 = im0 = im1 = 0.f;
+        if (++wp < wend) wcur = *wp;
       }
     }
   };
@@ -226,12 +231,12 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
     consume(sa, 0);
   }
   if constexpr (SUMS == 3) {
-    out_re[0] = re0;
-    out_im[0] = im0;
-    out_re[1] = rec;
-    out_im[1] = imc;
-    out_re[2] = res;
-    out_im[2] = ims;
+    out_re[0] = s0r;
+    out_im[0] = s0i;
+    out_re[1] = scr;
+    out_im[1] = sci;
+    out_re[2] = ssr;
+    out_im[2] = ssi;
   } else {
     out_re[0] = re0 + re1;
     out_im[0] = im0 + im1;
@@ -393,7 +398,7 @@ hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
     bp_tiles(f.n_rows, f.n_cols, &tx, &nt);
     if (f.n_rows < 1 || f.n_cols < 1 || f.n_chirps < 1 || f.n_ch < 1 || f.n_bins < 2 || f.n_ch % b.chg != 0 ||
         (b.form == kBpExact && (!f.rowv || !f.grpv)) || (b.form != kBpExact && (!f.rowq || !f.grpq)) ||
-        (b.sums == 3 && (!f.roww || (reinterpret_cast<uintptr_t>(f.roww) & 31))) || !f.out ||
+        (b.sums == 3 && (!f.roww || (reinterpret_cast<uintptr_t>(f.roww) & 7))) || !f.out ||
         f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.slot_base != slots ||
         f.chunk != (f.n_kb * nt + 7) / 8 ||
         (f.n_rows >= 8 && (f.n_rows + 15) / 16 > 0x7fffffff / 16) ||

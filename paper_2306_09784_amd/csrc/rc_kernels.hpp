@@ -118,9 +118,9 @@ struct BpFrame {
   // speed, so <P - q, kd v> / |P - q| is the Doppler index shift of one leg
   const float4* rowv;
   const float4* grpv;
-  // sub-aperture form (sums == 3): per row (cos, sin) of the chirp's window
-  // phase; the launch accumulates the plain sum and the two weighted sums
-  const float2* roww;
+  // sub-aperture form (sums == 3): per chirp (cos, sin) of its window phase;
+  // the launch accumulates the plain sum and the two weighted sums
+  const float2* roww;     // [n_chirps]
   float2* out;            // [n_kb][sums][n_pix]: image(s) (n_kb == 1) or partial images
   int n_chirps, n_ch, n_bins;
   int n_rows, n_cols;
