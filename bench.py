@@ -281,30 +281,71 @@ def paper_config(rc, synth, torch, steps):
     }
 
 
-def continuous_sar(rc, synth, torch, main_fps, n_sub=12, sub_cycles=128, K=4, depth=2):
+def make_drive(synth, torch, n_sub=24, sub_cycles=128):
+    """The plain-large sensor driving on for n_sub sub-apertures of sub_cycles
+    TDM cycles (one synthesis of the whole drive, cut into sub-apertures):
+    device and pinned host copies of each beat cube, geometry per sub-aperture."""
+    import dataclasses
+
+    cfg = dataclasses.replace(synth.CONFIGS["plain-large"], name="plain-large-stream", n_chirps=n_sub * sub_cycles)
+    t0 = time.perf_counter()
+    fr = synth.make_frame(cfg, device="cuda")
+    t_synth = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    subs = []
+    for j in range(n_sub):
+        sl = slice(j * sub_cycles, (j + 1) * sub_cycles)
+        host = torch.from_numpy(np.ascontiguousarray(fr.raw[sl]))
+        subs.append(dict(raw=host.to(dev), raw_pinned=host.pin_memory(), q_tx=np.ascontiguousarray(fr.q_tx[sl]),
+                         q_rx=np.ascontiguousarray(fr.q_rx[sl]), vel=np.ascontiguousarray(fr.vel[sl])))
+    pix = torch.from_numpy(np.ascontiguousarray(fr.pix)).to(dev)
+    return cfg, fr, subs, pix, t_synth
+
+
+def continuous_serving(rc, synth, torch, drive, capacity, sub_cycles=128, K=4, load=0.7, duration_s=20.0,
+                       max_batch=8):
+    """Sensors like the continuous-SAR one, each emitting a sub-aperture every
+    hop (its radar time, 128 cycles x 4 TX x T_P0 = 54.6 ms) from a random
+    phase, as many as make load x the measured aperture capacity; beat cubes
+    uploaded from pinned memory; the sensors share the synthesised drive
+    (each from its own offset; the drive's first sub-aperture starts a new
+    stream)."""
+    from paper_2306_09784_amd import serve
+
+    cfg, fr, subs, pix, _ = drive
+    hop = sub_cycles * cfg.n_tx * synth.RADAR["t_pri"]
+    n_sensors = max(1, int(load * capacity * hop))
+    pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=fr.n_fft, n_bins_max=fr.n_bins,
+                       n_chirps_max=sub_cycles, n_channels_max=cfg.n_channels, n_pix_max=fr.n_rows * fr.n_cols,
+                       max_frames_in_flight=16, max_detections=1 << 14, sliding_sensors=n_sensors,
+                       sliding_subapertures=K, sliding_depth=2)
+    drive_subs = [serve.SubAperture(s["raw_pinned"], s["q_tx"], s["q_rx"], s["vel"]) for s in subs]
+    sensors = [serve.ContinuousSensor(i, drive_subs, fr, pix, offset=(5 * i) % len(subs)) for i in range(n_sensors)]
+    srv = serve.ContinuousServer(pc, n_streams=2)
+    try:
+        with no_gc():
+            res = serve.run_continuous(srv, sensors, hop, duration_s, max_batch=max_batch)
+    finally:
+        srv.close()
+    res["load"] = load
+    return res
+
+
+def continuous_sar(rc, synth, torch, main_fps, drive, sub_cycles=128, K=4, depth=2):
     """Continuous SAR (the conclusion's continuous measurement): the large
     workload's sensor drives on; its stream is cut into sub-apertures of
     sub_cycles TDM cycles and every sub-aperture completes an aperture of the
     last K (K * sub_cycles = the large workload's 512 cycles, overlapping by
     (K - 1) / K).  Each chirp is back-projected once (three sums) and every
-    aperture is formed from the sums of its K sub-apertures.  Timed over the
-    full apertures (sub-apertures K - 1 .. n_sub - 1), two in flight."""
+    aperture is formed from the sums of its K sub-apertures.  The stream is
+    processed once untimed, then started again and timed over its full
+    apertures (sub-apertures K - 1 .. n_sub - 1), two in flight."""
     import dataclasses
 
-    base = synth.CONFIGS["plain-large"]
-    cfg = dataclasses.replace(base, name="plain-large-stream", n_chirps=n_sub * sub_cycles)
-    t0 = time.perf_counter()
-    fr = synth.make_frame(cfg, device="cuda")
-    t_synth = time.perf_counter() - t0
+    cfg, fr, subs, pix, t_synth = drive
+    n_sub = len(subs)
     dev = torch.device("cuda:0")
     S = sub_cycles
-    subs = []
-    for j in range(n_sub):
-        sl = slice(j * S, (j + 1) * S)
-        subs.append(dict(raw=torch.from_numpy(np.ascontiguousarray(fr.raw[sl])).to(dev),
-                         q_tx=np.ascontiguousarray(fr.q_tx[sl]), q_rx=np.ascontiguousarray(fr.q_rx[sl]),
-                         vel=np.ascontiguousarray(fr.vel[sl])))
-    pix = torch.from_numpy(np.ascontiguousarray(fr.pix)).to(dev)
     n_pix = fr.n_rows * fr.n_cols
     imgs = [torch.empty((n_pix, 2), dtype=torch.float32, device=dev) for _ in range(depth)]
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=fr.n_fft, n_bins_max=fr.n_bins,
@@ -322,7 +363,9 @@ def continuous_sar(rc, synth, torch, main_fps, n_sub=12, sub_cycles=128, K=4, de
                                        rc.RC_SLIDE_START if j == 0 else rc.RC_SLIDE_NEXT))
             plan.process([f], stream)
 
-        for j in range(K - 1):  # the stream's first, partial apertures
+        for j in list(range(n_sub)) + list(range(K - 1)):
+            # an untimed pass over the stream, then the restarted stream's
+            # first, partial apertures
             submit(j)
             plan.release(j)
         torch.cuda.synchronize()
@@ -441,7 +484,7 @@ def make_sensors(rc, synth, torch, n_sensors, seed=3000):
         fr = synth.make_frame(cfg, frame_index=i, device="cuda")
         raw = torch.from_numpy(fr.raw).pin_memory()
         pix = torch.from_numpy(fr.pix).to("cuda")
-        sensors.append(serve.SensorStream(i, fr, raw, pix))
+        sensors.append(serve.SensorStream(i, fr, raw, pix, raw.to("cuda")))
     return sensors
 
 
@@ -456,23 +499,30 @@ def mixed_plan_config(rc, synth, sensors, slots, **kw):
 
 
 def batched_mixed_median(rc, synth, torch, sensors, repeats=3, **kw):
-    """batched_mixed repeated; the run with the median throughput, plus every run's."""
+    """batched_mixed repeated; the run with the median throughput, plus every
+    run's; then the same with the beat cubes resident in HBM."""
     runs = [batched_mixed(rc, synth, torch, sensors, **kw) for _ in range(repeats)]
     runs.sort(key=lambda r: r["frames_per_s"])
     med = dict(runs[len(runs) // 2])
     med["frames_per_s_runs"] = [r["frames_per_s"] for r in runs]
+    res = sorted((batched_mixed(rc, synth, torch, sensors, resident=True, **kw) for _ in range(repeats)),
+                 key=lambda r: r["frames_per_s"])
+    med["resident"] = {"frames_per_s": res[len(res) // 2]["frames_per_s"],
+                       "frames_per_s_runs": [r["frames_per_s"] for r in res],
+                       "bp_terms_per_s_incl_all_stages": res[len(res) // 2]["bp_terms_per_s_incl_all_stages"]}
     return med
 
 
-def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32):
+def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=False):
     """Frames of mixed sizes in batches of `batch` frames per rc_process_batch
     (one back-projection launch per TX-group width and 16 frames), each batch
-    including the pinned-memory upload of its beat cubes.  Two batches are in
+    including the pinned-memory upload of its beat cubes (resident=False) or
+    with every cube already in HBM (resident=True).  Two batches are in
     flight on two streams: the host prepares and enqueues the next batch while
     the GPU processes the current one."""
     from paper_2306_09784_amd import serve
 
-    srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch), n_streams=2)
+    srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch), n_streams=2, resident=resident)
     try:
         order = [sensors[i % len(sensors)] for i in range(n_frames)]
         # warm-up batch
@@ -494,8 +544,14 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32):
     finally:
         srv.close()
     terms = sum(s.frame.n_rows * s.frame.n_cols * s.frame.cfg.n_chirps * s.frame.cfg.n_channels for s in order)
-    return {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "frames_per_s": n_frames / wall,
-            "bp_terms_per_s_incl_all_stages": terms / wall, "wall_s": wall}
+    out = {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "frames_per_s": n_frames / wall,
+           "bp_terms_per_s_incl_all_stages": terms / wall, "wall_s": wall, "inputs": (
+               "beat cubes resident in HBM" if resident else "beat cubes uploaded from pinned host memory")}
+    if not resident:
+        up = float(sum(s.frame.raw.nbytes for s in order))
+        out["upload_bytes"] = up
+        out["upload_gb_per_s"] = up / wall / 1e9
+    return out
 
 
 def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=64, max_batch=32):
@@ -579,7 +635,12 @@ def main(argv=None):
         print(json.dumps({"batched_mixed": batched_mixed_median(rc, synth, torch, sensors)}), flush=True)
         return 0
     if args.sliding_only:
-        print(json.dumps({"continuous_sar": continuous_sar(rc, synth, torch, None)}), flush=True)
+        drive = make_drive(synth, torch)
+        res = continuous_sar(rc, synth, torch, None, drive)
+        if args.serve_seconds > 0:
+            res["serving"] = continuous_serving(rc, synth, torch, drive, res["apertures_per_s"],
+                                                duration_s=args.serve_seconds / 3)
+        print(json.dumps({"continuous_sar": res}), flush=True)
         return 0
     cfg = synth.CONFIGS[args.workload]
     t0 = time.perf_counter()
@@ -659,8 +720,14 @@ def main(argv=None):
         progress("paper configuration done")
         out["tab2_ablation"] = ablation(rc, synth, torch)
         progress("Tab. II ablation done")
-        out["continuous_sar"] = continuous_sar(rc, synth, torch, out["value"])
+        drive = make_drive(synth, torch)
+        out["continuous_sar"] = continuous_sar(rc, synth, torch, out["value"], drive)
         progress(f"continuous SAR: {out['continuous_sar']['apertures_per_s']:.0f} apertures/s")
+        if args.serve_seconds > 0:
+            out["continuous_sar"]["serving"] = continuous_serving(
+                rc, synth, torch, drive, out["continuous_sar"]["apertures_per_s"], duration_s=args.serve_seconds / 3)
+            progress("continuous-SAR serving done")
+        del drive
         sensors = make_sensors(rc, synth, torch, 32)
         out["batched_mixed"] = batched_mixed_median(rc, synth, torch, sensors)
         progress(f"batched mixed: {out['batched_mixed']['frames_per_s']:.0f} frames/s")

@@ -35,6 +35,7 @@ class SensorStream:
     frame: object          # synth.Frame
     raw_pinned: object     # torch pinned CPU tensor, complex64 [M, CH, N_s]
     pix_dev: object        # torch device tensor, float32 [n_pix, 2]
+    raw_dev: object = None  # the beat cube already in HBM (Server(resident=True))
 
 
 @dataclasses.dataclass
@@ -50,17 +51,21 @@ class Completed:
 class Server:
     """Admits frames into the plan's slots and keeps several batches in flight."""
 
-    def __init__(self, plan_cfg: "_rc.PlanConfig", n_streams: int = 2, keep_images: bool = False):
+    def __init__(self, plan_cfg: "_rc.PlanConfig", n_streams: int = 2, keep_images: bool = False,
+                 resident: bool = False):
         import torch
 
         self.torch = torch
         self.cfg = plan_cfg
         self.plan = _rc.Plan(plan_cfg)
         self.n_slots = plan_cfg.max_frames_in_flight
+        self.resident = resident
         dev = torch.device("cuda")
         n_in = plan_cfg.n_chirps_max * plan_cfg.n_channels_max * plan_cfg.n_samples_max
-        # device input buffer per slot (the raw cube is copied in from pinned memory)
-        self.inputs = [torch.empty(n_in, dtype=torch.complex64, device=dev) for _ in range(self.n_slots)]
+        # device input buffer per slot (the raw cube is copied in from pinned
+        # memory), unless every sensor's cube is already resident in HBM
+        self.inputs = [] if resident else [torch.empty(n_in, dtype=torch.complex64, device=dev)
+                                            for _ in range(self.n_slots)]
         self.images = [torch.empty((plan_cfg.n_pix_max, 2), dtype=torch.float32, device=dev)
                        for _ in range(self.n_slots)] if keep_images else None
         self.free = list(range(self.n_slots))
@@ -88,9 +93,11 @@ class Server:
             for fid, sens, arrival in items:
                 slot = self.free.pop()
                 fr = sens.frame
-                n = fr.raw.size
-                dst = self.inputs[slot][:n]
-                dst.copy_(sens.raw_pinned.reshape(-1), non_blocking=True)
+                if self.resident:
+                    dst = sens.raw_dev
+                else:
+                    dst = self.inputs[slot][:fr.raw.size]
+                    dst.copy_(sens.raw_pinned.reshape(-1), non_blocking=True)
                 img = self.images[slot] if self.images is not None else None
                 descs.append(_rc.Plan.make_frame(
                     fid, data=dst, q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel, pixels=sens.pix_dev,
@@ -167,6 +174,180 @@ def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, dur
         "wall_s": wall,
         "frames_per_s": len(server.results) / wall,
         "offered_rate_hz": rate_hz,
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)) if len(lat) else None,
+        "max_ms": 1e3 * float(lat.max()) if len(lat) else None,
+        "worst_sensor_p99_ms": 1e3 * max(float(np.percentile(v, 99)) for v in per_sensor.values())
+        if per_sensor else None,
+    }
+
+
+# ---------------------------------------------------------------------------
+# Continuous SAR: sensors streaming sub-apertures (rc_sliding)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class SubAperture:
+    """One sub-aperture of a drive: beat cube in pinned host memory, geometry."""
+
+    raw_pinned: object     # torch pinned CPU tensor, complex64 [S, CH, N_s]
+    q_tx: np.ndarray       # float32 [S, CH, 2]
+    q_rx: np.ndarray
+    vel: np.ndarray        # float32 [S, 2]
+
+
+@dataclasses.dataclass
+class ContinuousSensor:
+    """A sensor that emits the sub-apertures of `drive` one hop apart, starting
+    at index `offset`; index 0 of the drive starts a new stream."""
+
+    sensor_id: int
+    drive: List[SubAperture]
+    frame: object          # synth.Frame giving the sizes, lattice and radar constants
+    pix_dev: object
+    offset: int = 0
+
+
+class ContinuousServer:
+    """Admits sub-apertures of many sensors into the plan's slots (at most the
+    plan's sliding_depth of one sensor at a time, in each sensor's order),
+    copies each beat cube from pinned memory into its slot and keeps batches in
+    flight on several streams; the plan forms every aperture."""
+
+    def __init__(self, plan_cfg: "_rc.PlanConfig", n_streams: int = 2, keep_images: bool = False):
+        import torch
+
+        self.torch = torch
+        self.plan = _rc.Plan(plan_cfg)
+        self.n_slots = plan_cfg.max_frames_in_flight
+        self.depth = plan_cfg.sliding_depth
+        dev = torch.device("cuda")
+        n_in = plan_cfg.n_chirps_max * plan_cfg.n_channels_max * plan_cfg.n_samples_max
+        self.inputs = [torch.empty(n_in, dtype=torch.complex64, device=dev) for _ in range(self.n_slots)]
+        self.images = [torch.empty((plan_cfg.n_pix_max, 2), dtype=torch.float32, device=dev)
+                       for _ in range(self.n_slots)] if keep_images else None
+        self.image_of: Dict[int, np.ndarray] = {}
+        self.sub_of: Dict[int, tuple] = {}     # frame_id -> (drive index, rc_sliding mode)
+        self.free = list(range(self.n_slots))
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.next_stream = 0
+        self.inflight: Dict[int, tuple] = {}   # frame_id -> (slot, sensor_id, arrival)
+        self.per_sensor = collections.Counter()
+        self.started = set()                     # sensors whose stream has begun
+        self.results: List[Completed] = []
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        self.plan.close()
+
+    def admissible(self, sensor_id: int) -> bool:
+        return bool(self.free) and self.per_sensor[sensor_id] < self.depth
+
+    def submit(self, items):
+        """items: (frame_id, ContinuousSensor, drive index, arrival time)."""
+        if not items:
+            return
+        torch = self.torch
+        stream = self.streams[self.next_stream]
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        descs = []
+        with torch.cuda.stream(stream):
+            for fid, sens, k, arrival in items:
+                slot = self.free.pop()
+                sub = sens.drive[k]
+                fr = sens.frame
+                dst = self.inputs[slot][:sub.raw_pinned.numel()]
+                dst.copy_(sub.raw_pinned.reshape(-1), non_blocking=True)
+                mode = _rc.RC_SLIDE_START if k == 0 or sens.sensor_id not in self.started else _rc.RC_SLIDE_NEXT
+                img = self.images[slot] if self.images is not None else None
+                descs.append(_rc.Plan.make_frame(
+                    fid, data=dst, q_tx=sub.q_tx, q_rx=sub.q_rx, vel=sub.vel, pixels=sens.pix_dev,
+                    n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
+                    n_samples=fr.cfg.n_samples, sensor_id=sens.sensor_id, height=fr.cfg.height,
+                    image_out=img, sliding=mode))
+                self.started.add(sens.sensor_id)
+                self.sub_of[fid] = (k, mode)
+                self.inflight[fid] = (slot, sens.sensor_id, arrival)
+                self.per_sensor[sens.sensor_id] += 1
+        self.plan.process(descs, stream)
+
+    def harvest(self) -> int:
+        n = 0
+        for fid in list(self.inflight):
+            if not self.plan.poll(fid):
+                continue
+            slot, sid, arrival = self.inflight.pop(fid)
+            dets = self.plan.detections(fid)
+            done = time.perf_counter()
+            if self.images is not None:
+                self.torch.cuda.synchronize()
+                self.image_of[fid] = self.images[slot].cpu().numpy().copy()
+            self.plan.release(fid)
+            self.free.append(slot)
+            self.per_sensor[sid] -= 1
+            self.results.append(Completed(fid, sid, arrival, arrival, done, dets))
+            n += 1
+        return n
+
+
+def run_continuous(server: ContinuousServer, sensors: List[ContinuousSensor], hop_s: float, duration_s: float,
+                   seed: int = 4100, max_batch: Optional[int] = None) -> dict:
+    """Each sensor emits its next sub-aperture every hop_s (the radar time a
+    sub-aperture takes), from a random phase; sub-apertures wait in arrival
+    order and are admitted as slots and each sensor's depth allow.  Returns
+    throughput and latency (arrival to detections on the host) statistics."""
+    rng = np.random.default_rng(seed)
+    events = []
+    for s in sensors:
+        phase = rng.uniform(0.0, hop_s)
+        n = int((duration_s - phase) / hop_s) + 1
+        for j in range(n):
+            t = phase + j * hop_s
+            if t < duration_s:
+                events.append((t, s, (s.offset + j) % len(s.drive)))
+    events.sort(key=lambda e: e[0])
+    queue = collections.deque()
+    max_batch = max_batch or server.n_slots
+    t0 = time.perf_counter()
+    i, fid = 0, 1
+    while i < len(events) or queue or server.inflight:
+        now = time.perf_counter() - t0
+        while i < len(events) and events[i][0] <= now:
+            t, s, k = events[i]
+            queue.append((fid, s, k, t0 + t))
+            fid += 1
+            i += 1
+        server.harvest()
+        batch, held = [], set()
+        # in arrival order; a sensor whose earlier sub-aperture must wait holds
+        # back its later ones
+        for item in list(queue):
+            if len(batch) == max_batch or not server.free or len(batch) == len(server.free):
+                break
+            sid = item[1].sensor_id
+            if sid in held:
+                continue
+            if server.per_sensor[sid] + sum(1 for b in batch if b[1].sensor_id == sid) < server.depth:
+                batch.append(item)
+            else:
+                held.add(sid)
+        for item in batch:
+            queue.remove(item)
+        if batch:
+            server.submit(batch)
+        elif not queue and i < len(events) and not server.inflight:
+            time.sleep(max(0.0, min(events[i][0] - (time.perf_counter() - t0), 1e-3)))
+    wall = time.perf_counter() - t0
+    lat = np.array([r.done - r.arrival for r in server.results])
+    per_sensor = collections.defaultdict(list)
+    for r in server.results:
+        per_sensor[r.sensor_id].append(r.done - r.arrival)
+    return {
+        "sensors": len(sensors),
+        "subapertures": len(server.results),
+        "wall_s": wall,
+        "apertures_per_s": len(server.results) / wall,
+        "offered_per_s": len(sensors) / hop_s,
+        "hop_ms": 1e3 * hop_s,
         "p50_ms": 1e3 * float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_ms": 1e3 * float(np.percentile(lat, 99)) if len(lat) else None,
         "max_ms": 1e3 * float(lat.max()) if len(lat) else None,

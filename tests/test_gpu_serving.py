@@ -94,3 +94,52 @@ def test_burst_waits_for_slots(rc, torch):
         assert len(srv.free) == 2 and not srv.inflight
     finally:
         srv.close()
+
+
+def test_continuous_sar_serving_equals_streams_alone(rc, torch):
+    """Sensors streaming sub-apertures at their own hops, admitted into shared
+    batches on two streams (at most two of a sensor in flight): each aperture
+    equals the one its sensor's stream gives processed alone, bitwise."""
+    from paper_2306_09784_amd import serve
+
+    K, S, n_sub = 3, 8, 6
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="drive", n_samples=64, n_chirps=n_sub * S,
+                              n_rx=4, nx=40, ny=33, box=(-4.0, 4.0, 1.5, 7.0), seed=700)
+    fr = synth.make_frame(cfg)
+    drive = [serve.SubAperture(torch.from_numpy(np.ascontiguousarray(fr.raw[j * S:(j + 1) * S])).pin_memory(),
+                               np.ascontiguousarray(fr.q_tx[j * S:(j + 1) * S]),
+                               np.ascontiguousarray(fr.q_rx[j * S:(j + 1) * S]),
+                               np.ascontiguousarray(fr.vel[j * S:(j + 1) * S])) for j in range(n_sub)]
+    pix = torch.from_numpy(fr.pix).to("cuda")
+    sensors = [serve.ContinuousSensor(i, drive, fr, pix, offset=(2 * i) % n_sub) for i in range(4)]
+    pc = SC.plan_config(rc, [fr], n_chirps_max=S, max_frames_in_flight=6, sliding_sensors=4,
+                        sliding_subapertures=K, sliding_depth=2)
+    srv = serve.ContinuousServer(pc, n_streams=2, keep_images=True)
+    try:
+        res = serve.run_continuous(srv, sensors, hop_s=0.004, duration_s=0.1, seed=11, max_batch=4)
+        assert res["subapertures"] == len(srv.results) >= 80
+        by_sensor = {}
+        for r in sorted(srv.results, key=lambda r: r.frame_id):
+            by_sensor.setdefault(r.sensor_id, []).append(r)
+        n_pix = fr.n_rows * fr.n_cols
+        # each sensor's sequence again, alone, on a plan of one sensor
+        ref_cfg = dataclasses.replace(pc, sliding_sensors=1, max_frames_in_flight=2)
+        with rc.Plan(ref_cfg) as plan:
+            dev = torch.device("cuda")
+            for sid, rs in by_sensor.items():
+                for r in rs:
+                    k, mode = srv.sub_of[r.frame_id]
+                    sub = drive[k]
+                    img = torch.empty((n_pix, 2), dtype=torch.float32, device=dev)
+                    raw = sub.raw_pinned.to(dev)
+                    f = rc.Plan.make_frame(1, data=raw, q_tx=sub.q_tx, q_rx=sub.q_rx, vel=sub.vel, pixels=pix,
+                                           n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft,
+                                           fs=fr.fs, n_samples=cfg.n_samples, image_out=img, sliding=mode)
+                    plan.process([f])
+                    dets = plan.detections(1)
+                    torch.cuda.synchronize()
+                    plan.release(1)
+                    assert np.array_equal(srv.image_of[r.frame_id][:n_pix], img.cpu().numpy()), (sid, r.frame_id)
+                    assert np.array_equal(r.detections, dets), (sid, r.frame_id)
+    finally:
+        srv.close()

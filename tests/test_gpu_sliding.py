@@ -44,11 +44,12 @@ def rc():
     return mod
 
 
-def _stream(n_blocks, S, nx=40, ny=32, n_rx=4, seed=31, speed=4.0, yaw=0.0, n_samples=128):
+def _stream(n_blocks, S, nx=40, ny=32, n_rx=4, seed=31, speed=4.0, yaw=0.0, n_samples=128, n_tx=1,
+            height=0.0):
     """One continuous drive cut into n_blocks sub-apertures of S chirps."""
     cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="stream", n_samples=n_samples,
-                              n_chirps=n_blocks * S, nx=nx, ny=ny, n_rx=n_rx, seed=seed, speed=speed,
-                              yaw_rate=yaw)
+                              n_chirps=n_blocks * S, nx=nx, ny=ny, n_rx=n_rx, n_tx=n_tx, seed=seed,
+                              speed=speed, yaw_rate=yaw, height=height)
     fr = synth.make_frame(cfg)
     blocks = []
     for j in range(n_blocks):
@@ -171,6 +172,24 @@ def test_sliding_stream_parity(rc, torch, precision, exact):
         assert ratio <= 1.0, f"aperture {b}: per-pixel bound exceeded by {ratio:.3f}"
     _report(f"sliding_{name}", max_rel=worst_rel, apertures=nb)
     assert worst_rel <= (SPLIT_TOL if precision == SPLIT else PLAIN_TOL)
+
+
+@pytest.mark.parametrize("n_tx,n_rx,height", [(2, 2, 0.0), (1, 3, 0.8), (1, 1, 0.0), (4, 2, 0.5)],
+                         ids=["tdm2x2", "rx3-height", "rx1", "tdm4x2-height"])
+def test_sliding_channel_layouts(rc, torch, n_tx, n_rx, height):
+    """The chirp's channel sum joins the three sums at the end of every chirp:
+    TX groups narrower than a chirp (several pipeline stages per chirp), odd
+    and single channel counts (one-row stages), antennas above the pixels."""
+    K, S, nb = 2, 12, 4
+    fr, blocks = _stream(nb, S, n_tx=n_tx, n_rx=n_rx, height=height, seed=41 + n_rx, nx=24, ny=20)
+    with rc.Plan(_plan_cfg(rc, fr, S, K)) as plan:
+        got = _Runner(rc, torch, plan, fr).run(blocks, per_batch=2)
+    k, ob = _oracle_blocks(fr, blocks)
+    for b in range(nb):
+        P = O.bp_sliding(fr.pix.astype(np.float64), ob, b, K, k["a1"], k["a2"], k["kd"], height=height)
+        err = np.abs(got[b][0].astype(np.complex128) - P)
+        ratio = float((err / _bound(fr, k, ob, b, K, PLAIN, np.abs(P).max())).max())
+        assert ratio <= 1.0, f"aperture {b}: per-pixel bound exceeded by {ratio:.3f}"
 
 
 def test_sliding_detections_match_oracle(rc, torch):
