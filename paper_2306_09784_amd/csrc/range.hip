@@ -13,9 +13,12 @@
 // n_bins bins that are written, directly in the interleaved (value, slope)
 // layout that back-projection gathers with one 16-byte load per term, with
 // the chirp window w_sar[m] folded in.  Pass p of radix R at stride Ns
-// multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (loaded from a
-// full-circle twiddle table the host evaluates in double) and writes output r
-// to (b / Ns) Ns R + (b mod Ns) + r Ns.  LDS rows are padded by one element
+// multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (loaded from the
+// frame's n_fft-point full-circle twiddle table, which the host evaluates in
+// double) and writes output r to (b / Ns) Ns R + (b mod Ns) + r Ns.  When every
+// row of a launch has at most n_fft / 2 samples (zero padding by two or more,
+// the usual case), the upper half of every first-pass butterfly's inputs is
+// zero at compile time: neither loaded nor computed.  LDS rows are padded by one element
 // per 16, which keeps the stride-16 writes of the first passes free of bank
 // conflicts.  Rows shorter than 16 x 64 samples share a workgroup.  Samples,
 // the range window and twiddles are read through buffer descriptors: the
@@ -116,8 +119,9 @@ struct RowIo {
 };
 
 // One Stockham pass of radix R at stride NS over the E samples of this lane
-// (E / R butterflies b = j + T u).
-template <int LOG2N, int R, int NS, bool FIRST, bool LAST>
+// (E / R butterflies b = j + T u).  HALF (first pass only): inputs r >= R / 2
+// lie at or beyond n_fft / 2 >= n_s, i.e. in the zero padding.
+template <int LOG2N, int R, int NS, bool FIRST, bool LAST, bool HALF = false>
 __device__ __forceinline__ void fft_pass(const RangeArgs& a, const RowIo& io, float2* buf, int j) {
   using F = Fft<LOG2N>;
   constexpr int N = F::N, E = F::E, T = F::T, B = E / R;
@@ -128,8 +132,8 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, const RowIo& io, fl
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int b = j + T * u;
-      // byte offset of W_{NS R}^{(b mod NS) r} in the full-circle table, stepped in r
-      const unsigned step = (unsigned)((b & (NS - 1)) << (a.tw_log2 - lg)) * 8u;
+      // byte offset of W_{NS R}^{(b mod NS) r} in the n_fft-point table, stepped in r
+      const unsigned step = (unsigned)((b & (NS - 1)) << (LOG2N - lg)) * 8u;
       unsigned off = step;
 #pragma unroll
       for (int r = 1; r < R; ++r, off += step) {
@@ -144,6 +148,12 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, const RowIo& io, fl
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = b + r * (N / R);
+      if constexpr (FIRST && HALF) {
+        if (r >= R / 2) {
+          v[u * R + r] = make_float2(0.f, 0.f);
+          continue;
+        }
+      }
       if constexpr (FIRST) {
         // zero padding and dead rows read past the descriptor, which returns zeros
         const unsigned off = (io.live && i < a.n_s) ? io.row_off + (unsigned)i * 8u : 0xfffffff0u;
@@ -185,7 +195,7 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, const RowIo& io, fl
   __syncthreads();
 }
 
-template <int LOG2N>
+template <int LOG2N, bool HALF>
 __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeMulti m) {
   using F = Fft<LOG2N>;
   __shared__ float2 lds[F::RPW * F::PADN];
@@ -201,13 +211,13 @@ __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeMulti m) 
   io.row_off = (unsigned)(row * a.n_s) * 8u;
   io.live = live;
   io.win = __builtin_amdgcn_make_buffer_rsrc((void*)a.w_range, (short)0, a.n_s * 4, kRsrcWord3);
-  io.tw = __builtin_amdgcn_make_buffer_rsrc((void*)a.twiddle, (short)0, 8 << a.tw_log2, kRsrcWord3);
+  io.tw = __builtin_amdgcn_make_buffer_rsrc((void*)a.twiddle, (short)0, 8 << LOG2N, kRsrcWord3);
 
   if constexpr (LOG2N < 4) {
-    fft_pass<LOG2N, F::N, 1, true, true>(a, io, buf, j);
+    fft_pass<LOG2N, F::N, 1, true, true, HALF>(a, io, buf, j);
   } else {
     constexpr int P16 = LOG2N / 4, REM = LOG2N % 4;
-    fft_pass<LOG2N, 16, 1, true, P16 == 1 && REM == 0>(a, io, buf, j);
+    fft_pass<LOG2N, 16, 1, true, P16 == 1 && REM == 0, HALF>(a, io, buf, j);
     if constexpr (P16 >= 2) fft_pass<LOG2N, 16, 16, false, P16 == 2 && REM == 0>(a, io, buf, j);
     if constexpr (P16 >= 3) fft_pass<LOG2N, 16, 256, false, REM == 0>(a, io, buf, j);
     if constexpr (REM > 0) fft_pass<LOG2N, (1 << REM), (1 << (4 * P16)), false, true>(a, io, buf, j);
@@ -230,14 +240,19 @@ template <int LOG2N>
 hipError_t launch_fft(RangeMulti m, hipStream_t s) {
   using F = Fft<LOG2N>;
   int64_t grid = 0;
+  bool half = true;
   for (int i = 0; i < m.n_frames; ++i) {
     m.begin[i] = (int)grid;
     grid += (m.f[i].rows + F::RPW - 1) / F::RPW;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    half = half && 2 * m.f[i].n_s <= F::N;
   }
   m.begin[m.n_frames] = (int)grid;
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(range_compress_kernel<LOG2N>, dim3((unsigned)grid), dim3(kThreads), 0, s, m);
+  if (half)
+    hipLaunchKernelGGL((range_compress_kernel<LOG2N, true>), dim3((unsigned)grid), dim3(kThreads), 0, s, m);
+  else
+    hipLaunchKernelGGL((range_compress_kernel<LOG2N, false>), dim3((unsigned)grid), dim3(kThreads), 0, s, m);
   return hipGetLastError();
 }
 
@@ -264,7 +279,7 @@ hipError_t launch_range_compress(const RangeMulti& m, hipStream_t s) {
     const RangeArgs& a = m.f[i];
     if (a.rows < 0 || a.n_fft < 4 || (a.n_fft & (a.n_fft - 1)) || (1 << a.log2n) != a.n_fft ||
         a.n_fft > 4096 || a.log2n != log2n || a.n_s < 1 || a.n_s > a.n_fft || a.n_bins < 1 ||
-        a.n_bins > a.n_fft || a.n_ch < 1 || a.tw_log2 < a.log2n || a.tw_log2 > 12 ||
+        a.n_bins > a.n_fft || a.n_ch < 1 || a.tw_log2 != a.log2n || !a.twiddle ||
         a.rows * a.n_s * 8 >= (int64_t(1) << 31))
       return hipErrorInvalidValue;
   }
