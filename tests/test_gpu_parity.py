@@ -349,6 +349,14 @@ def test_abi_errors_on_device(rc, torch):
         plan.release(3)
         plan.process([mk(4)])
         plan.release(4)
+    # a destroyed plan: the binding passes a null handle, which every entry
+    # point rejects
+    with pytest.raises(rc.RcError) as ei:
+        plan.process([mk(5)])
+    assert ei.value.status == rc.RC_EINVAL
+    with pytest.raises(rc.RcError) as ei:
+        plan.release(4)
+    assert ei.value.status == rc.RC_EINVAL
 
 
 # ---------------------------------------------------------------------------
