@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define RC_ABI_VERSION 3
+#define RC_ABI_VERSION 4
 
 typedef enum rc_status {
   RC_OK = 0,
@@ -184,6 +184,16 @@ typedef struct rc_frame {
                                    spectrum_out are the sub-aperture's own.  No
                                    double-precision recheck (near-threshold cells
                                    are flagged RC_DET_NEAR_THRESHOLD).            */
+  const float* w_sar;           /* host [n_chirps]: the chirp window w_sar[m] of
+                                   Alg. 2 (Sec. III-B), finite; NULL: the plan's
+                                   window.  Not with sub-apertures (their window
+                                   spans the aperture).                           */
+  const float* f_doppler;       /* device [n_rows * n_cols]: the Doppler index
+                                   f_doppler(p) of Alg. 2 in bins, e.g. from a
+                                   caller's own velocity estimate; NULL: the plan
+                                   computes it from the mean velocity at the
+                                   aperture centre (Sec. III-D).  Not with
+                                   RC_DOPPLER_EXACT (Alg. 1 has no such table). */
 } rc_frame;
 
 #define RC_DET_NEAR_THRESHOLD 1u  /* in the band, decided in single precision */

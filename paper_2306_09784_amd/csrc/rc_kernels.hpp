@@ -88,6 +88,7 @@ struct TableArgs {
   double a1;                      // bins per wavelength of path
   float* fbase;                   // [n_pix] (split only)
   double height;                  // antennas above the pixel plane, metres
+  const float* fd_in;             // [n_pix] caller's f_doppler (bins) or nullptr
 };
 using TableMulti = Multi<TableArgs, 16>;
 hipError_t launch_pixel_tables(const TableMulti& m, hipStream_t s);
@@ -230,6 +231,7 @@ struct RecheckArgs {
   double inv_lam;           // turns per metre of path
   double qt_x, qt_y, qr_x, qr_y, v_x, v_y;  // mean TX and RX positions and mean velocity (Doppler table)
   double height;            // antennas above the pixel plane, metres
+  const float* fd_in;       // [n_pix] caller's f_doppler (bins) or nullptr
   double* power;            // [cap][(2 half + 1)^2] scratch
   unsigned long long* mask;
   int words_per_row;

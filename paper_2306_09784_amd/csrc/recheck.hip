@@ -53,7 +53,9 @@ __global__ __launch_bounds__(kThreads) void recheck_pixels_kernel(RecheckArgs a)
     const double px = pf.x, py = pf.y;
     const double h2 = a.height * a.height;
     double fd = 0.0;
-    if (!a.exact) {
+    if (a.fd_in) {
+      fd = (double)a.fd_in[(int64_t)r * a.n_cols + c];
+    } else if (!a.exact) {
       double d0;
       fd = a.kd * (radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, h2, &d0) +
                    radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y, h2, &d0));

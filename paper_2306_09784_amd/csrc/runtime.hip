@@ -324,6 +324,17 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
   for (int64_t i = 0; i < 2 * (int64_t)f.n_chirps; ++i)
     if (!std::isfinite(f.vel[i]))
       return fail(RC_EINVAL, "frame %lld: non-finite velocity", (long long)f.frame_id);
+  if (f.w_sar) {
+    if (f.sliding != RC_SLIDE_OFF)
+      return fail(RC_EINVAL, "frame %lld: a sub-aperture takes the plan's window (it spans the aperture)",
+                  (long long)f.frame_id);
+    for (int m = 0; m < f.n_chirps; ++m)
+      if (!std::isfinite(f.w_sar[m]))
+        return fail(RC_EINVAL, "frame %lld: non-finite w_sar", (long long)f.frame_id);
+  }
+  if (f.f_doppler && d.doppler == RC_DOPPLER_EXACT)
+    return fail(RC_EINVAL, "frame %lld: f_doppler with RC_DOPPLER_EXACT (Alg. 1 has no Doppler table)",
+                (long long)f.frame_id);
   if (f.sliding != RC_SLIDE_OFF) {
     if (f.sliding != RC_SLIDE_NEXT && f.sliding != RC_SLIDE_START)
       return fail(RC_EINVAL, "frame %lld: unknown sliding mode %d", (long long)f.frame_id, (int)f.sliding);
@@ -457,7 +468,10 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
     for (int64_t r = 0; r < rows; ++r)
       geo_m[r] = make_float4(f.q_tx[2 * r], f.q_tx[2 * r + 1], f.q_rx[2 * r], f.q_rx[2 * r + 1]);
     for (int m = 0; m < f.n_chirps; ++m) vel_m[m] = make_float2(f.vel[2 * m], f.vel[2 * m + 1]);
-    make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar64);
+    if (f.w_sar)
+      for (int m = 0; m < f.n_chirps; ++m) w_sar64[m] = f.w_sar[m];
+    else
+      make_window(d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar64);
     make_window(d.range_window, d.range_kaiser_beta, n_s, w_range64);
   }
   if (sl) {
@@ -477,7 +491,10 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   float* w_sar = g + 8 * rows + metres;
   // a sub-aperture's table is unwindowed: the window enters when the
   // aperture is formed from the sums
-  make_window(sl ? RC_WIN_RECT : d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
+  if (f.w_sar)
+    std::memcpy(w_sar, f.w_sar, (size_t)f.n_chirps * sizeof(float));
+  else
+    make_window(sl ? RC_WIN_RECT : d.sar_window, d.sar_kaiser_beta, f.n_chirps, w_sar);
   float* w_range = w_sar + f.n_chirps;
   make_window(d.range_window, d.range_kaiser_beta, n_s, w_range);
   const size_t geo_bytes = (size_t)(8 * rows + metres + f.n_chirps + n_s) * sizeof(float);
@@ -548,6 +565,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   ta.a1 = a1 * lam;
   ta.fbase = s.fbase;
   ta.height = f.height;
+  ta.fd_in = f.f_doppler;
 
   // back-projection descriptor (Alg. 2), launched batch-wide by the caller
   float2* img = f.image_out ? static_cast<float2*>(f.image_out) : s.image;
@@ -603,6 +621,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
     rk.qr_x = ta.qr_x; rk.qr_y = ta.qr_y;
     rk.v_x = vx; rk.v_y = vy;
     rk.height = f.height;
+    rk.fd_in = f.f_doppler;
   }
   out->chg = chg;
   out->sums = planes;

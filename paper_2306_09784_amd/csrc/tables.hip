@@ -13,7 +13,9 @@
 // that restores the rounding of |P|^2 to first order: back-projection forms
 // d^2 = |P|^2 + |q|^2 - 2 P.q, so a rounding delta of |P|^2 shortens each of
 // the two distances of a path by delta / (2 d) ~ delta / (2 |P|).
-// Everything is evaluated in double (O(pixels) work) and rounded once.
+// Everything is evaluated in double (O(pixels) work) and rounded once.  A
+// caller-supplied Doppler table replaces the computed one (and enters the
+// split form's reference index).
 //
 // Split-phase form: a two-way path is written 2R + delta_tx + delta_rx with
 // R = |P| (the path via the aperture centre) and delta = |P - q| - R, a
@@ -45,9 +47,10 @@ __global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableMulti m) {
   const float2 p = a.pix[i];
   const double px = p.x, py = p.y;
   const double h2m = a.height * a.height;
-  const double r = radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, h2m) +
-                   radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y, h2m);
-  a.fd[i] = (float)(a.kd * r);
+  const double fdop = a.fd_in ? (double)a.fd_in[i]
+                              : a.kd * (radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, h2m) +
+                                        radial(px, py, a.qr_x, a.qr_y, a.v_x, a.v_y, h2m));
+  a.fd[i] = (float)fdop;
   const double lx = (px - a.c_x) * a.inv_lam, ly = (py - a.c_y) * a.inv_lam;
   const double hl = a.height * a.inv_lam;
   // |P|^2 + h^2: the squared distance to the aperture centre, which carries the
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableMulti m) {
   } else if (a.split) {
     const double two_r = 2.0 * R;
     a.pixc[i] = make_float4((float)lx, (float)ly, (float)R, (float)(two_r - floor(two_r)));
-    a.fbase[i] = (float)(a.a1 * two_r + a.kd * r);
+    a.fbase[i] = (float)(a.a1 * two_r + fdop);
   } else {
     const double corr = R > 0.0 ? (pp - (double)ppf) / R : 0.0;
     a.pixc[i] = make_float4((float)lx, (float)ly, ppf, (float)corr);

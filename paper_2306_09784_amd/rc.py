@@ -16,7 +16,7 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librc.so")
 
-RC_ABI_VERSION = 3
+RC_ABI_VERSION = 4
 
 # rc_status
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_ETRUNC, RC_EHIP, RC_ENOTREADY, RC_ENOTFOUND = range(7)
@@ -96,6 +96,8 @@ class rc_frame(C.Structure):
         ("spectrum_out", C.c_void_p),
         ("height", C.c_double),
         ("sliding", C.c_int),
+        ("w_sar", C.c_void_p),
+        ("f_doppler", C.c_void_p),
     ]
 
 
@@ -304,19 +306,24 @@ class Plan:
                    pixels, n_rows: int, n_cols: int, n_bins: int, n_fft: int, fs: float,
                    n_samples: int = 0, input_kind: int = RC_INPUT_RAW, image_out=None,
                    doppler_out=None, spectrum_out=None, sensor_id: int = 0, height: float = 0.0,
-                   sliding: int = RC_SLIDE_OFF) -> rc_frame:
-        """Builds an rc_frame.  q_tx, q_rx, vel must be C-contiguous float32
-        host arrays that stay alive until rc_process_batch returns."""
-        for a in (q_tx, q_rx, vel):
+                   sliding: int = RC_SLIDE_OFF, w_sar: Optional[np.ndarray] = None,
+                   f_doppler=None) -> rc_frame:
+        """Builds an rc_frame.  q_tx, q_rx, vel (and w_sar, if given) must be
+        C-contiguous float32 host arrays that stay alive until rc_process_batch
+        returns; f_doppler is a device tensor of one float per pixel."""
+        for a in (q_tx, q_rx, vel) + ((w_sar,) if w_sar is not None else ()):
             if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags.c_contiguous):
-                raise TypeError("q_tx, q_rx and vel must be C-contiguous float32 numpy arrays")
+                raise TypeError("q_tx, q_rx, vel and w_sar must be C-contiguous float32 numpy arrays")
         M, CH = q_tx.shape[0], q_tx.shape[1]
         if q_tx.shape != (M, CH, 2) or q_rx.shape != (M, CH, 2) or vel.shape != (M, 2):
             raise ValueError("geometry shapes must be q [M, CH, 2], vel [M, 2]")
+        if w_sar is not None and w_sar.shape != (M,):
+            raise ValueError("w_sar must have one weight per chirp")
         return rc_frame(frame_id, sensor_id, n_samples, n_fft, n_bins, M, CH, fs, input_kind,
                         _ptr(data), q_tx.ctypes.data, q_rx.ctypes.data, vel.ctypes.data,
                         _ptr(pixels), n_rows, n_cols, _ptr(image_out), _ptr(doppler_out),
-                        _ptr(spectrum_out), float(height), int(sliding))
+                        _ptr(spectrum_out), float(height), int(sliding),
+                        w_sar.ctypes.data if w_sar is not None else None, _ptr(f_doppler))
 
     def process(self, frames, stream=None) -> int:
         arr = (rc_frame * len(frames))(*frames)

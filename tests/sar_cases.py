@@ -38,8 +38,10 @@ def to_device(frame, torch):
 
 
 def run_gpu(rc, plan, frame, torch, frame_id=1, spectrum=None, want_spectrum=False,
-            want_doppler=False, keep=False):
-    """Process one frame; returns dict(image, detections, spectrum?, doppler?) as numpy."""
+            want_doppler=False, keep=False, w_sar=None, f_doppler=None):
+    """Process one frame; returns dict(image, detections, spectrum?, doppler?) as numpy.
+    w_sar (float32 [n_chirps]) and f_doppler (float32 [n_pix]) replace the
+    plan's chirp window and the computed Doppler table."""
     dev = torch.device("cuda")
     t = to_device(frame, torch)
     n_pix = frame.n_rows * frame.n_cols
@@ -60,7 +62,10 @@ def run_gpu(rc, plan, frame, torch, frame_id=1, spectrum=None, want_spectrum=Fal
                             pixels=t["pix"], n_rows=frame.n_rows, n_cols=frame.n_cols,
                             n_bins=frame.n_bins, n_fft=frame.n_fft, fs=frame.fs,
                             n_samples=frame.cfg.n_samples, input_kind=kind, image_out=img,
-                            doppler_out=dop_out, spectrum_out=spec_out, height=frame.cfg.height)
+                            doppler_out=dop_out, spectrum_out=spec_out, height=frame.cfg.height,
+                            w_sar=None if w_sar is None else np.ascontiguousarray(w_sar, dtype=np.float32),
+                            f_doppler=None if f_doppler is None else
+                            torch.from_numpy(np.ascontiguousarray(f_doppler, dtype=np.float32)).to(dev))
     plan.process([fr])
     dets = plan.detections(frame_id)
     torch.cuda.synchronize()
@@ -79,9 +84,10 @@ def oracle_constants(frame):
 
 
 def run_oracle(frame, spectrum=None, pix_index=None, sar_window="hann", range_window="hann",
-               cfar=(2, 8, 1e-4), doppler="average"):
+               cfar=(2, 8, 1e-4), doppler="average", w_sar=None, f_doppler=None):
     """FP64 pipeline; with pix_index only those pixels are formed (no CFAR).
-    doppler="exact" forms the image with Alg. 1 instead of Alg. 2."""
+    doppler="exact" forms the image with Alg. 1 instead of Alg. 2; w_sar and
+    f_doppler (the values the GPU was given) replace the window and table."""
     k = oracle_constants(frame)
     if spectrum is None:
         s = O.range_compress(frame.raw, O.window(range_window, frame.cfg.n_samples), frame.n_fft,
@@ -92,8 +98,13 @@ def run_oracle(frame, spectrum=None, pix_index=None, sar_window="hann", range_wi
     if pix_index is not None:
         pix = pix[pix_index]
     h = frame.cfg.height
-    fd = O.doppler_table(pix, frame.q_tx, frame.q_rx, frame.vel, k["kd"], height=h)
-    w = O.window(sar_window, frame.cfg.n_chirps)
+    if f_doppler is None:
+        fd = O.doppler_table(pix, frame.q_tx, frame.q_rx, frame.vel, k["kd"], height=h)
+    else:
+        fd = np.asarray(f_doppler, dtype=np.float32).astype(np.float64)
+        fd = fd if pix_index is None else fd[pix_index]
+    w = O.window(sar_window, frame.cfg.n_chirps) if w_sar is None else \
+        np.asarray(w_sar, dtype=np.float32).astype(np.float64)
     if doppler == "exact":
         P = O.bp_alg1(pix, frame.q_tx, frame.q_rx, frame.vel, s, w, R["f0"], k["mu"], k["df"], height=h)
     else:

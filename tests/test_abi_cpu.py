@@ -56,7 +56,7 @@ int main(void) {
   P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, max_rechecks) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
   P(rc_plan_desc, sliding_sensors) P(rc_plan_desc, sliding_subapertures) P(rc_plan_desc, sliding_depth)
   P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
-  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out) P(rc_frame, height) P(rc_frame, sliding)
+  P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out) P(rc_frame, height) P(rc_frame, sliding) P(rc_frame, w_sar) P(rc_frame, f_doppler)
   P(rc_detection, threshold) P(rc_detection, flags)
   return 0;
 }

@@ -310,6 +310,34 @@ def test_plain_large_sampled_pixels(rc, torch, precision):
 # ---------------------------------------------------------------------------
 # ABI behaviour on the device
 # ---------------------------------------------------------------------------
+def _caller_inputs(fr, seed):
+    """A chirp window and a Doppler table of the caller's own: positive
+    weights in [0.2, 1.2] and the computed table moved by up to +-2 bins."""
+    rng = np.random.default_rng(seed)
+    k = SC.oracle_constants(fr)
+    w = (0.2 + rng.random(fr.cfg.n_chirps)).astype(np.float32)
+    fd = O.doppler_table(fr.pix.astype(np.float64), fr.q_tx, fr.q_rx, fr.vel, k["kd"])
+    fd = (fd + rng.uniform(-2.0, 2.0, fd.shape)).astype(np.float32)
+    return w, fd
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_caller_window_and_doppler_table(rc, torch, precision):
+    """Alg. 2 with the caller's w_sar and f_doppler (its inputs in the
+    paper's statement of the problem) against the oracle given the same."""
+    fr = SC.small_frame(nx=64, ny=48, n_chirps=48)
+    w, fd = _caller_inputs(fr, 61)
+    kw = dict(precision=rc.RC_PREC_FP32_SPLIT if precision == SPLIT else rc.RC_PREC_FP32)
+    with rc.Plan(SC.plan_config(rc, [fr], **kw)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, want_doppler=True, w_sar=w, f_doppler=fd)
+    assert np.array_equal(out["doppler"], fd)          # the table is taken as given
+    ora = SC.run_oracle(fr, cfar=None, w_sar=w, f_doppler=fd)
+    _check_image("caller_inputs", fr, out["image"], ora, precision)
+    # not the plan's own window and table: the images differ far beyond the bound
+    own = SC.run_oracle(fr, cfar=None)
+    assert np.abs(own["image"] - ora["image"]).max() > 0.1 * np.abs(ora["image"]).max()
+
+
 def test_abi_errors_on_device(rc, torch):
     fr = SC.small_frame(nx=96, ny=96)
     cfg = SC.plan_config(rc, [fr], max_frames_in_flight=1, max_detections=1)
@@ -349,6 +377,17 @@ def test_abi_errors_on_device(rc, torch):
         plan.release(3)
         plan.process([mk(4)])
         plan.release(4)
+        # a caller's window with a non-finite weight, a window of a sub-aperture
+        w = np.ones(fr.cfg.n_chirps, np.float32)
+        w[3] = np.nan
+        with pytest.raises(rc.RcError) as ei:
+            plan.process([mk(6, w_sar=w)])
+        assert ei.value.status == rc.RC_EINVAL
+    with rc.Plan(SC.plan_config(rc, [fr], doppler=rc.RC_DOPPLER_EXACT)) as plan:
+        fd = torch.zeros(96 * 96, dtype=torch.float32, device="cuda")
+        with pytest.raises(rc.RcError) as ei:                # Alg. 1 has no Doppler table
+            plan.process([mk(7, f_doppler=fd)])
+        assert ei.value.status == rc.RC_EINVAL and "f_doppler" in rc.last_error()
     # a destroyed plan: the binding passes a null handle, which every entry
     # point rejects
     with pytest.raises(rc.RcError) as ei:

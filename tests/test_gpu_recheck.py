@@ -160,6 +160,19 @@ def _check(name, frame, ora, out, table_err, cap=None):
     return k
 
 
+def test_recheck_caller_window_and_doppler_table(rc, torch):
+    """The recheck forms its pixels in double with the caller's window and
+    Doppler table too."""
+    from tests.test_gpu_parity import _caller_inputs
+
+    fr = SC.small_frame(nx=160, ny=160)
+    w, fd = _caller_inputs(fr, 62)
+    with rc.Plan(SC.plan_config(rc, [fr], cfar_margin_rel=MARGIN, max_rechecks=1 << 16)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, w_sar=w, f_doppler=fd)
+    ora = SC.run_oracle(fr, cfar=(GUARD, TRAIN, PFA), w_sar=w, f_doppler=fd)
+    _check("caller_inputs", fr, ora, out, _table_bound(ora["spectrum"], ora["w_sar"]))
+
+
 @pytest.mark.parametrize("precision", [pytest.param(PLAIN, id="fp32"), pytest.param(SPLIT, id="split")])
 def test_recheck_end_to_end(rc, torch, precision):
     fr = SC.small_frame(nx=192, ny=192)
