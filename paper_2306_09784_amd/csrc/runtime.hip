@@ -118,7 +118,6 @@ struct Sensor {
   const float* pixels = nullptr;
   double height = 0;
   hipEvent_t done = nullptr;  // recorded after the stream's last aperture was formed
-  hipStream_t stream = nullptr;
   bool recorded = false;
 };
 
@@ -903,13 +902,14 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
       return undo(fail(RC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)));        \
   } while (0)
   const bool timed = p->d.stage_timing != 0;
-  // sub-apertures whose stream's previous aperture was formed on another
-  // stream wait for it (their aperture reads its partial images)
+  // a sensor's sub-apertures wait for its previous aperture (theirs read its
+  // partial images), whichever stream formed it; on the same stream the wait
+  // is already implied, and a handle equal to the last one may still name a
+  // new stream, so the wait is always recorded
   for (size_t k = 0; k < sensors.size(); ++k) {
     bool used = false;
     for (int i = 0; i < n_frames && !used; ++i) used = slide[i].sensor == (int)k;
-    if (used && p->sensors[k].recorded && p->sensors[k].stream != st)
-      RC_BATCH(hipStreamWaitEvent(st, p->sensors[k].done, 0));
+    if (used && p->sensors[k].recorded) RC_BATCH(hipStreamWaitEvent(st, p->sensors[k].done, 0));
   }
   // host part of every frame: geometry upload, argument blocks
   for (int i = 0; i < n_frames; ++i) {
@@ -1040,7 +1040,6 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     for (int i = 0; i < n_frames && !used; ++i) used = slide[i].sensor == (int)k;
     if (!used) continue;
     RC_BATCH(hipEventRecord(sensors[k].done, st));
-    sensors[k].stream = st;
     sensors[k].recorded = true;
   }
   if (timed)
