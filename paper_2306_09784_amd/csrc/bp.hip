@@ -36,7 +36,9 @@
 // windowed aperture, instead of back-projecting every chirp once per
 // aperture it belongs to.  All channels of a chirp share its weights, so the
 // terms of a chirp accumulate as usual and their sum enters the three sums
-// once per chirp (a dozen instructions per chirp and pixel).
+// once per chirp (a dozen instructions per chirp and pixel).  The three sums
+// live in the lane's own LDS slot between chirps, which keeps the register
+// count, and so the occupancy, of the single-sum kernel.
 //
 // Work distribution: one launch covers a batch of frames; its work items are
 // (frame, chirp block, 16 x 16 tile).  Workgroups are dispatched to the eight
@@ -117,8 +119,14 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   // per-pixel index base: plain f_doppler; split the index of the reference path
   const float fb = fidx;
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
-  // SUMS == 3: the plain, cos- and sin-weighted sums over the chirps done
-  float s0r = 0.f, s0i = 0.f, scr = 0.f, sci = 0.f, ssr = 0.f, ssi = 0.f;
+  // SUMS == 3: the plain, cos- and sin-weighted sums over the chirps done,
+  // in this lane's LDS slot my[0] = (re: plain, cos, sin), my[1] = (im: ...)
+  __shared__ float3 sums[SUMS == 3 ? 2 * kThreads : 1];
+  float3* my = sums + (SUMS == 3 ? 2 * threadIdx.x : 0);
+  if constexpr (SUMS == 3) {
+    my[0] = make_float3(0.f, 0.f, 0.f);
+    my[1] = make_float3(0.f, 0.f, 0.f);
+  }
   float2 wcur = SUMS == 3 ? wp[0] : make_float2(0.f, 0.f);
   int chirp_rows = 0;  // rows of the current chirp consumed (wave-uniform)
   Leg<FORM> tx;
@@ -178,8 +186,8 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       const float cs = __builtin_amdgcn_cosf(st.turn[j]);
       const float vr = fmaf(st.phi[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
       const float vi = fmaf(st.phi[j], __uint_as_float(st.e[j].w), __uint_as_float(st.e[j].y));
-      // (cs - i sn) (vr + i vi)
-      if (((U == 1) ? par : j) & 1) {
+      // (cs - i sn) (vr + i vi); the sub-aperture form keeps one accumulator pair
+      if (SUMS == 1 && (((U == 1) ? par : j) & 1)) {
         re1 = fmaf(cs, vr, re1);
         re1 = fmaf(sn, vi, re1);
         im1 = fmaf(cs, vi, im1);
@@ -197,14 +205,16 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       chirp_rows += U;
       if (chirp_rows == a.n_ch) {
         chirp_rows = 0;
-        const float tr = re0 + re1, ti = im0 + im1;
-        s0r += tr;
-        s0i += ti;
-        scr = fmaf(wcur.x, tr, scr);
-        sci = fmaf(wcur.x, ti, sci);
-        ssr = fmaf(wcur.y, tr, ssr);
-        ssi = fmaf(wcur.y, ti, ssi);
-        re0 = re1 = im0 = im1 = 0.f;
+        float3 sr = my[0], si = my[1];
+        sr.x += re0;
+        si.x += im0;
+        sr.y = fmaf(wcur.x, re0, sr.y);
+        si.y = fmaf(wcur.x, im0, si.y);
+        sr.z = fmaf(wcur.y, re0, sr.z);
+        si.z = fmaf(wcur.y, im0, si.z);
+        my[0] = sr;
+        my[1] = si;
+        re0 = im0 = 0.f;
         if (++wp < wend) wcur = *wp;
       }
     }
@@ -231,12 +241,13 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
     consume(sa, 0);
   }
   if constexpr (SUMS == 3) {
-    out_re[0] = s0r;
-    out_im[0] = s0i;
-    out_re[1] = scr;
-    out_im[1] = sci;
-    out_re[2] = ssr;
-    out_im[2] = ssi;
+    const float3 sr = my[0], si = my[1];
+    out_re[0] = sr.x;
+    out_im[0] = si.x;
+    out_re[1] = sr.y;
+    out_im[1] = si.y;
+    out_re[2] = sr.z;
+    out_im[2] = si.z;
   } else {
     out_re[0] = re0 + re1;
     out_im[0] = im0 + im1;
