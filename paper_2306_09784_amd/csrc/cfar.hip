@@ -113,8 +113,11 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
 // Ordered compaction of one frame's detection mask: each sweep covers
 // 1024 x 8 consecutive mask words; a thread counts its eight words, the
 // workgroup scans the thread totals (wave scans, then a scan of the 16 wave
-// totals), and every thread copies the records of its words' set bits in
-// order.  Output order is ascending pixel index.
+// totals), every thread writes the cell index of each set bit of its words
+// to its output slot, and then all threads copy the sweep's records from
+// those cells in parallel (detections cluster, so a thread may own many set
+// bits: copying them one by one would chain that many memory latencies).
+// Output order is ascending pixel index.
 __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m) {
   const CompactArgs a = m.f[__builtin_amdgcn_readfirstlane((int)blockIdx.x)];  // one workgroup per frame
   __shared__ int wave_sum[kCompactThreads / 64];
@@ -154,8 +157,7 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m
         while (bits) {
           const int b = __ffsll((long long)bits) - 1;
           bits &= bits - 1;
-          const int64_t cell = r * a.n_cols + cb + b;
-          if (pos < a.cap) a.det_out[pos] = a.det_cell[cell];
+          if (pos < a.cap) a.det_out[pos].pixel = (int)(r * a.n_cols + cb + b);
           ++pos;
         }
       }
@@ -163,6 +165,8 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m
     __syncthreads();
     if (threadIdx.x == kCompactThreads - 1) base_sh = pos;  // the last thread ends the sweep
     __syncthreads();
+    const int64_t end = base_sh < a.cap ? base_sh : a.cap;
+    for (int64_t i = base + threadIdx.x; i < end; i += kCompactThreads) a.det_out[i] = a.det_cell[a.det_out[i].pixel];
   }
   if (threadIdx.x == 0) *a.count = base_sh;
 }
