@@ -267,6 +267,8 @@ def paper_config(rc, synth, torch, steps):
                      f"aperture {L:.3f} m; {in_box} pixels inside the 30 m x 30 m box)"),
         "frames_per_s": run["fps"],
         "ms_per_frame": 1e3 / run["fps"],
+        "stages_ms": {"range": float(run["stages"][:, 0].mean()), "tables": float(run["stages"][:, 1].mean()),
+                      "backprojection": bp_ms, "detection": float(run["stages"][:, 3].mean())},
         "backprojection_ms": bp_ms,
         "bp_terms_per_s": terms / (bp_ms * 1e-3),
         "p99_ms": 1e3 * float(np.percentile(run["lat"], 99)),
