@@ -176,29 +176,33 @@ def cpu_baseline(frame, budget_s: float = 20.0, procs: int = 16):
 
 def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup,
                   doppler=0, want_image=False, depth=2):
-    """Times `steps` frames through rc_process_batch + rc_detections on one
-    stream, `depth` frames in flight: frame i + 1 is prepared on the host and
-    enqueued while the GPU still processes frame i (a sensor streams frames
-    back to back).  Latency is per frame, from its submission to its
+    """Times `steps` frames through rc_process_batch + rc_detections, `depth`
+    frames in flight: frame i + 1 is prepared on the host and enqueued while
+    the GPU still processes frame i (a sensor streams frames back to back).
+    With two or more in flight, frames alternate between two HIP streams (each
+    with its own image buffer), so one frame's short stages run beside the
+    other's back-projection.  Latency is per frame, from its submission to its
     detections on the host."""
     dev = torch.device("cuda:0")
     cfg = frame.cfg
     raw = torch.from_numpy(frame.raw).to(dev)
     pix = torch.from_numpy(np.ascontiguousarray(pix_host)).to(dev)
     n_pix = n_rows * n_cols
-    img = torch.empty((n_pix, 2), dtype=torch.float32, device=dev)
+    n_streams = 2 if depth >= 2 else 1
+    imgs = [torch.empty((n_pix, 2), dtype=torch.float32, device=dev) for _ in range(n_streams)]
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
                        n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
                        n_pix_max=n_pix, max_frames_in_flight=max(2, depth), max_detections=1 << 16,
                        precision=precision, doppler=doppler, stage_timing=True)
-    stream = torch.cuda.current_stream()
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
     lat, stages, n_det = [], [], 0
     with rc.Plan(pc) as plan:
         def submit(fid):
             fr = rc.Plan.make_frame(fid, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
                                     n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins, n_fft=frame.n_fft,
-                                    fs=frame.fs, n_samples=cfg.n_samples, image_out=img, height=cfg.height)
-            plan.process([fr], stream)
+                                    fs=frame.fs, n_samples=cfg.n_samples, image_out=imgs[fid % n_streams],
+                                    height=cfg.height)
+            plan.process([fr], streams[fid % n_streams])
 
         for i in range(warmup):
             submit(i)
@@ -224,8 +228,8 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
             torch.cuda.synchronize()
             total = time.perf_counter() - t_start
     res = {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
-    if want_image:
-        res["image"] = img.cpu().numpy().view(np.complex64).reshape(-1)
+    if want_image:  # the last frame's
+        res["image"] = imgs[(1000 + steps - 1) % n_streams].cpu().numpy().view(np.complex64).reshape(-1)
     return res
 
 
@@ -242,9 +246,10 @@ def paper_config(rc, synth, torch, steps):
     in_box = int(np.sum((pix[:, 0] >= x0) & (pix[:, 0] <= x1) & (pix[:, 1] >= y0) & (pix[:, 1] <= y1)))
     run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, steps, 1,
                         want_image=True)
+    one = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, 10, 1, depth=1)
     n_pix = g["nth"] * g["nr"]
     terms = float(n_pix) * cfg.n_chirps * cfg.n_channels
-    bp_ms = float(run["stages"][:, 2].mean())
+    bp_ms = float(one["stages"][:, 2].mean())
     # Fig. 3's comparison: the polar image shown on the 2.5 cm Cartesian grid
     # (rc_resample_polar) against the image formed on that grid directly
     cart = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_PREC_FP32, 1, 1,
@@ -267,11 +272,11 @@ def paper_config(rc, synth, torch, steps):
                      f"aperture {L:.3f} m; {in_box} pixels inside the 30 m x 30 m box)"),
         "frames_per_s": run["fps"],
         "ms_per_frame": 1e3 / run["fps"],
-        "stages_ms": {"range": float(run["stages"][:, 0].mean()), "tables": float(run["stages"][:, 1].mean()),
-                      "backprojection": bp_ms, "detection": float(run["stages"][:, 3].mean())},
+        "stages_ms": {"range": float(one["stages"][:, 0].mean()), "tables": float(one["stages"][:, 1].mean()),
+                      "backprojection": bp_ms, "detection": float(one["stages"][:, 3].mean())},
         "backprojection_ms": bp_ms,
         "bp_terms_per_s": terms / (bp_ms * 1e-3),
-        "p99_ms": 1e3 * float(np.percentile(run["lat"], 99)),
+        "p99_ms": 1e3 * float(np.percentile(one["lat"], 99)),
         "polar_on_cartesian": {
             "resample_ms": e0.elapsed_time(e1),
             "target_gain_db_vs_cartesian_image": _target_gain_db(shown_h, frame.pix, frame.targets,
@@ -354,7 +359,9 @@ def continuous_sar(rc, synth, torch, main_fps, drive, sub_cycles=128, K=4, depth
                        n_chirps_max=S, n_channels_max=cfg.n_channels, n_pix_max=n_pix,
                        max_frames_in_flight=depth, max_detections=1 << 16, stage_timing=True,
                        sliding_sensors=1, sliding_subapertures=K, sliding_depth=depth)
-    stream = torch.cuda.current_stream()
+    # sub-apertures alternate between two streams; the plan orders each
+    # aperture after the sensor's previous one
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
     stages, lat = [], []
     with rc.Plan(pc) as plan:
         def submit(j):
@@ -363,12 +370,16 @@ def continuous_sar(rc, synth, torch, main_fps, drive, sub_cycles=128, K=4, depth
                                    n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
                                    n_samples=cfg.n_samples, image_out=imgs[j % depth], sliding=(
                                        rc.RC_SLIDE_START if j == 0 else rc.RC_SLIDE_NEXT))
-            plan.process([f], stream)
+            plan.process([f], streams[j % 2])
 
-        for j in list(range(n_sub)) + list(range(K - 1)):
-            # an untimed pass over the stream, then the restarted stream's
+        for n, j in enumerate(list(range(n_sub)) + list(range(K - 1))):
+            # an untimed pass over the stream, one sub-aperture at a time (its
+            # full apertures give the stage times: kernels of concurrent
+            # sub-apertures would overlap), then the restarted stream's
             # first, partial apertures
             submit(j)
+            if K - 1 <= n < n_sub:
+                stages.append(plan.stage_times(j))
             plan.release(j)
         torch.cuda.synchronize()
         with no_gc():
@@ -382,7 +393,6 @@ def continuous_sar(rc, synth, torch, main_fps, drive, sub_cycles=128, K=4, depth
                     done = queue.pop(0)
                     plan.detections(done)
                     lat.append(time.perf_counter() - t_sub[done])
-                    stages.append(plan.stage_times(done))
                     if done != n_sub - 1:
                         plan.release(done)
             torch.cuda.synchronize()
@@ -463,7 +473,7 @@ def ablation(rc, synth, torch, steps=3):
     out, ref_ms, ref_img = {}, None, None
     for name, (fr, pix, nr, nc, dop) in runs.items():
         run = time_pipeline(rc, synth, torch, fr, pix, nr, nc, rc.RC_PREC_FP32, steps, 1, doppler=dop,
-                            want_image=True)
+                            want_image=True, depth=1)
         bp_ms = float(run["stages"][:, 2].mean())
         ref_ms = ref_ms or bp_ms
         if ref_img is None:
@@ -653,7 +663,10 @@ def main(argv=None):
     # frame latency alone (one frame in flight)
     lat_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
                             rc.RC_PREC_FP32, 10, 1, depth=1)
-    stages = main_run["stages"]
+    # per-stage device times (and the roofline) from the single-frame run: with
+    # two frames on two streams, kernels of different frames overlap and a
+    # launch's duration no longer measures the launch alone
+    stages = lat_run["stages"]
     n_pix = frame.n_rows * frame.n_cols
     progress(f"main workload: {main_run['fps']:.1f} frames/s")
 
@@ -678,8 +691,9 @@ def main(argv=None):
         "ms_per_step": 1e3 * total / args.steps,
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-        "latency_note": "p50/p99: submission to detections on the host, one frame in flight (10 frames); "
-                        "value and ms_per_step: frames streamed back to back, two in flight",
+        "latency_note": "p50/p99 and stages_ms: submission to detections on the host and device stage times, "
+                        "one frame in flight (10 frames); value and ms_per_step: frames streamed back to back, "
+                        "two in flight on two streams",
         "streamed_p50_ms": 1e3 * float(np.percentile(main_run["lat"], 50)),
         "higher_is_better": True,
         "scaling": "weak",
@@ -707,6 +721,10 @@ def main(argv=None):
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": measured_traffic(args.workload),
+            "measured": "HIP events around each back-projection launch of the one-frame-in-flight run (the "
+                        "same launches as the streamed run, without other frames' kernels beside them)",
+            # the same flops per frame over the streamed time per frame, all stages included
+            "streamed_frac": contrib * flops / (total / args.steps) / 1e12 / peak,
         },
         "synth_s": t_synth,
     }
@@ -714,9 +732,11 @@ def main(argv=None):
         # the same frame with the split-phase (high-accuracy) form
         sp = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
                            rc.RC_PREC_FP32_SPLIT, max(5, args.steps // 2), 1)
+        sp1 = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
+                            rc.RC_PREC_FP32_SPLIT, 5, 1, depth=1)
         out["split_phase_form"] = {
-            "frames_per_s": sp["fps"], "backprojection_ms": float(sp["stages"][:, 2].mean()),
-            "p99_ms": 1e3 * float(np.percentile(sp["lat"], 99))}
+            "frames_per_s": sp["fps"], "backprojection_ms": float(sp1["stages"][:, 2].mean()),
+            "p99_ms": 1e3 * float(np.percentile(sp1["lat"], 99))}
         progress("split-phase form done")
         out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
         progress("paper configuration done")

@@ -30,6 +30,16 @@ __device__ __forceinline__ int multi_frame(const M& m, int w) {
   return __builtin_amdgcn_readfirstlane(fi);
 }
 
+// Per-frame geometry from mapped pinned host memory (src, the device address
+// of the staging buffer) to device memory, n16 16-byte units.
+struct UploadArgs {
+  float4* dst;
+  const float4* src;
+  int64_t n16;
+};
+using UploadMulti = Multi<UploadArgs, 32>;
+hipError_t launch_upload(const UploadMulti& m, hipStream_t s);
+
 // Range compression (beat signal -> beat spectrum): windowed, zero-padded
 // radix-2 decimation-in-time FFT per (chirp, channel) row in LDS, cropped to
 // n_bins.  Writes the interpolation table of back-projection: for bin k the

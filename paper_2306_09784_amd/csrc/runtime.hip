@@ -94,8 +94,10 @@ struct Slot {
   double* rpower = nullptr;   // recomputed window powers of the listed cells
   double2* spec64 = nullptr;  // beat spectrum in double for the recheck
   rc::RecheckArgs rk{};       // geometry part filled by prepare_frame
-  // pinned host
+  // pinned host (staging: mapped and coherent, read by the upload kernel
+  // through staging_dev)
   float* staging = nullptr;
+  const float4* staging_dev = nullptr;
   int64_t* h_count = nullptr;
   rc_detection* h_det = nullptr;
   hipEvent_t done = nullptr;
@@ -193,7 +195,8 @@ size_t geo_floats(const rc_plan_desc& d) {
   const size_t rows = (size_t)d.n_chirps_max * d.n_channels_max;
   const size_t metres = d.max_rechecks > 0 ? recheck_floats(rows, d.n_chirps_max, d.n_samples_max) : 0;
   const size_t weights = d.sliding_sensors > 0 ? 2 * rows : 0;
-  return rows * 8 + std::max(metres, weights) + d.n_chirps_max + d.n_samples_max;
+  // rounded up to whole 16-byte units for the upload kernel
+  return (rows * 8 + std::max(metres, weights) + d.n_chirps_max + d.n_samples_max + 3) & ~size_t(3);
 }
 
 SlotSizes slot_sizes(const rc_plan_desc& d) {
@@ -384,6 +387,9 @@ int tx_group(const rc_frame& f) {
 
 // What a frame contributes to the batch-wide launches.
 struct Prepared {
+  rc::UploadArgs up{};
+  bool recheck = false;
+  rc::Range64Args r6{};
   bool raw_in = true;
   rc::RangeArgs ra{};
   rc::PairArgs pa{};
@@ -497,13 +503,11 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   float* w_range = w_sar + f.n_chirps;
   make_window(d.range_window, d.range_kaiser_beta, n_s, w_range);
   const size_t geo_bytes = (size_t)(8 * rows + metres + f.n_chirps + n_s) * sizeof(float);
-  RC_HIP(hipMemcpyAsync(s.rowgeo, s.staging, geo_bytes, hipMemcpyHostToDevice, st));
+  out->up = rc::UploadArgs{s.rowgeo, s.staging_dev, (int64_t)((geo_bytes + 15) / 16)};
   const float4* d_rowq = s.rowgeo;
   const float4* d_grpq = s.rowgeo + rows;
   const float* d_wsar = reinterpret_cast<const float*>(s.rowgeo) + 8 * rows + metres;
   const float* d_wrange = d_wsar + f.n_chirps;
-  const bool timed = d.stage_timing != 0;
-  if (timed) RC_HIP(hipEventRecord(s.stage_ev[0], st));
 
   // 1. beat spectrum -> interpolation table (launched batch-wide)
   out->raw_in = f.input_kind == RC_INPUT_RAW;
@@ -543,7 +547,8 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
     r6.n_fft = raw_in ? f.n_fft : 0;
     r6.log2n = raw_in ? ilog2(f.n_fft) : 0;
     r6.n_bins = f.n_bins;
-    RC_HIP(rc::launch_range64(r6, st));
+    out->recheck = true;
+    out->r6 = r6;
   }
 
   // 2. per-frame tables: Doppler (Sec. III-D) and local pixel coordinates
@@ -806,7 +811,12 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     s.spec64 = sz.spec64 ? reinterpret_cast<double2*>(take(sz.spec64)) : nullptr;
     s.det_count = reinterpret_cast<int64_t*>(take(64));
     s.n_listed = reinterpret_cast<int*>(s.det_count + 1);
-    e = hipHostMalloc(reinterpret_cast<void**>(&s.staging), geo_bytes, hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void**>(&s.staging), geo_bytes, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+      void* dev = nullptr;
+      e = hipHostGetDevicePointer(&dev, s.staging, 0);
+      s.staging_dev = static_cast<const float4*>(dev);
+    }
     if (e == hipSuccess) {
       const size_t hb = 64 + (size_t)std::min(kDetPrefix, desc->max_detections) * sizeof(rc_detection);
       e = hipHostMalloc(reinterpret_cast<void**>(&s.h_count), hb, hipHostMallocDefault);
@@ -902,15 +912,6 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
       return undo(fail(RC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)));        \
   } while (0)
   const bool timed = p->d.stage_timing != 0;
-  // a sensor's sub-apertures wait for its previous aperture (theirs read its
-  // partial images), whichever stream formed it; on the same stream the wait
-  // is already implied, and a handle equal to the last one may still name a
-  // new stream, so the wait is always recorded
-  for (size_t k = 0; k < sensors.size(); ++k) {
-    bool used = false;
-    for (int i = 0; i < n_frames && !used; ++i) used = slide[i].sensor == (int)k;
-    if (used && p->sensors[k].recorded) RC_BATCH(hipStreamWaitEvent(st, p->sensors[k].done, 0));
-  }
   // host part of every frame: geometry upload, argument blocks
   for (int i = 0; i < n_frames; ++i) {
     for (Slot& c : p->slots)
@@ -918,6 +919,17 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     rc_status r = prepare_frame(p, *slot[i], frames[i], slide[i].sensor >= 0 ? &slide[i] : nullptr, st, &prep[i]);
     if (r != RC_OK) return undo(r);
   }
+  // 0: every frame's geometry from its staging buffer, one launch per 32 frames
+  for (int i0 = 0; i0 < n_frames; i0 += rc::UploadMulti::kMax) {
+    rc::UploadMulti m;
+    for (int i = i0; i < n_frames && m.n_frames < rc::UploadMulti::kMax; ++i) m.f[m.n_frames++] = prep[i].up;
+    RC_BATCH(rc::launch_upload(m, st));
+  }
+  if (timed)
+    for (Slot* q : slot) RC_BATCH(hipEventRecord(q->stage_ev[0], st));
+  // the recheck's beat spectra in double
+  for (int i = 0; i < n_frames; ++i)
+    if (prep[i].recheck) RC_BATCH(rc::launch_range64(prep[i].r6, st));
   // 1: range compression, one launch per DFT length and 32 frames
   {
     std::vector<char> done(n_frames, 0);
@@ -1001,6 +1013,17 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     }
   }
   if (rb.n_frames) RC_BATCH(rc::launch_reduce_partials(rb, st));
+  // a sensor's apertures read the partial images of its earlier
+  // sub-apertures: wait for the aperture the sensor formed last, whichever
+  // stream formed it (on the same stream the wait is implied; a handle equal
+  // to the last one may still name a new stream, so it is always recorded).
+  // Back-projection before this point only writes the sub-apertures' own
+  // ring slots, which no pending aperture reads (the ring holds K + depth - 1)
+  for (size_t k = 0; k < sensors.size(); ++k) {
+    bool used = false;
+    for (int i = 0; i < n_frames && !used; ++i) used = slide[i].sensor == (int)k;
+    if (used && p->sensors[k].recorded) RC_BATCH(hipStreamWaitEvent(st, p->sensors[k].done, 0));
+  }
   // continuous SAR: each sub-aperture's aperture from the ring.  The window
   // over the aperture's N = K S chirps starts at chirp a = (b - K + 1) S of the
   // stream: w(m) = 1/2 - 1/2 cos(theta_m - phi), phi = 2 pi (a mod (N - 1)) / (N - 1)
