@@ -175,20 +175,21 @@ def cpu_baseline(frame, budget_s: float = 20.0, procs: int = 16):
 
 
 def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup,
-                  doppler=0, want_image=False, depth=2):
+                  doppler=0, want_image=False, depth=2, n_streams=None):
     """Times `steps` frames through rc_process_batch + rc_detections, `depth`
     frames in flight: frame i + 1 is prepared on the host and enqueued while
     the GPU still processes frame i (a sensor streams frames back to back).
-    With two or more in flight, frames alternate between two HIP streams (each
-    with its own image buffer), so one frame's short stages run beside the
-    other's back-projection.  Latency is per frame, from its submission to its
-    detections on the host."""
+    With two or more in flight, frames alternate between n_streams HIP streams
+    (default two, each with its own image buffer), so one frame's short stages
+    run beside the other's back-projection.  Latency is per frame, from its
+    submission to its detections on the host."""
     dev = torch.device("cuda:0")
     cfg = frame.cfg
     raw = torch.from_numpy(frame.raw).to(dev)
     pix = torch.from_numpy(np.ascontiguousarray(pix_host)).to(dev)
     n_pix = n_rows * n_cols
-    n_streams = 2 if depth >= 2 else 1
+    if n_streams is None:
+        n_streams = 2 if depth >= 2 else 1
     imgs = [torch.empty((n_pix, 2), dtype=torch.float32, device=dev) for _ in range(n_streams)]
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
                        n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
@@ -244,8 +245,11 @@ def paper_config(rc, synth, torch, steps):
     pix = rc.grid_polar(g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"])
     x0, x1, y0, y1 = cfg.box
     in_box = int(np.sum((pix[:, 0] >= x0) & (pix[:, 0] <= x1) & (pix[:, 1] >= y0) & (pix[:, 1] <= y1)))
+    # one stream: frames this short (four or five generations of waves)
+    # would overlap for most of their back-projection on two streams, and two
+    # frames' tables in each XCD's L2 cost more than the overlap gains
     run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, steps, 1,
-                        want_image=True)
+                        want_image=True, n_streams=1)
     one = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, 10, 1, depth=1)
     n_pix = g["nth"] * g["nr"]
     terms = float(n_pix) * cfg.n_chirps * cfg.n_channels
@@ -606,6 +610,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain-large")
+    ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
+                    help="HIP streams the main workload's frames alternate over (1 for profiling: kernels of "
+                         "different frames then never overlap, so per-dispatch counters stay attributable)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="duration of the Poisson serving run (0 disables it)")
@@ -659,7 +666,7 @@ def main(argv=None):
     frame = synth.make_frame(cfg, device="cuda")
     t_synth = time.perf_counter() - t0
     main_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                             rc.RC_PREC_FP32, args.steps, args.warmup)
+                             rc.RC_PREC_FP32, args.steps, args.warmup, n_streams=args.streams)
     # frame latency alone (one frame in flight)
     lat_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
                             rc.RC_PREC_FP32, 10, 1, depth=1)
@@ -693,7 +700,7 @@ def main(argv=None):
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "latency_note": "p50/p99 and stages_ms: submission to detections on the host and device stage times, "
                         "one frame in flight (10 frames); value and ms_per_step: frames streamed back to back, "
-                        "two in flight on two streams",
+                        f"two in flight on {args.streams} stream(s)",
         "streamed_p50_ms": 1e3 * float(np.percentile(main_run["lat"], 50)),
         "higher_is_better": True,
         "scaling": "weak",
