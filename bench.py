@@ -175,7 +175,7 @@ def cpu_baseline(frame, budget_s: float = 20.0, procs: int = 16):
 
 
 def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup,
-                  doppler=0, want_image=False, depth=2, n_streams=None):
+                  doppler=0, want_image=False, depth=2, n_streams=None, plan_kw=None):
     """Times `steps` frames through rc_process_batch + rc_detections, `depth`
     frames in flight: frame i + 1 is prepared on the host and enqueued while
     the GPU still processes frame i (a sensor streams frames back to back).
@@ -194,9 +194,10 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
                        n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
                        n_pix_max=n_pix, max_frames_in_flight=max(2, depth), max_detections=1 << 16,
-                       precision=precision, doppler=doppler, stage_timing=True)
+                       precision=precision, doppler=doppler, stage_timing=True, **(plan_kw or {}))
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
     lat, stages, n_det = [], [], 0
+    last_dets = None
     with rc.Plan(pc) as plan:
         def submit(fid):
             fr = rc.Plan.make_frame(fid, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
@@ -222,13 +223,15 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
                 while len(queue) >= depth or (i == steps - 1 and queue):
                     done = queue.pop(0)
                     dets = plan.detections(done)
+                    last_dets = dets
                     lat.append(time.perf_counter() - t_sub[done])
                     stages.append(plan.stage_times(done))
                     plan.release(done)
                     n_det = len(dets)
             torch.cuda.synchronize()
             total = time.perf_counter() - t_start
-    res = {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det}
+    res = {"total_s": total, "fps": steps / total, "lat": lat, "stages": np.array(stages), "n_det": n_det,
+           "detections": last_dets}
     if want_image:  # the last frame's
         res["image"] = imgs[(1000 + steps - 1) % n_streams].cpu().numpy().view(np.complex64).reshape(-1)
     return res
@@ -745,6 +748,20 @@ def main(argv=None):
             "frames_per_s": sp["fps"], "backprojection_ms": float(sp1["stages"][:, 2].mean()),
             "p99_ms": 1e3 * float(np.percentile(sp1["lat"], 99))}
         progress("split-phase form done")
+        # the same frame with the double-precision recheck of near-threshold cells
+        rk = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_PREC_FP32, 5, 1,
+                           depth=1, plan_kw=dict(max_rechecks=4096))
+        flags = rk["detections"]["flags"]
+        out["fp64_recheck"] = {
+            "max_rechecks": 4096, "cfar_margin_rel": 0.03,
+            # the double FFT of the frame runs with range compression, the
+            # double back-projection of the listed cells with detection
+            "range_ms": float(rk["stages"][:, 0].mean()), "range_ms_without": float(stages[:, 0].mean()),
+            "detection_ms": float(rk["stages"][:, 3].mean()),
+            "detection_ms_without": float(stages[:, 3].mean()),
+            "detections": int(len(flags)), "decided_in_fp64": int(((flags & rc.RC_DET_RECHECKED) != 0).sum()),
+            "still_near_threshold": int(((flags & rc.RC_DET_NEAR_THRESHOLD) != 0).sum())}
+        progress("recheck done")
         out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
         progress("paper configuration done")
         out["tab2_ablation"] = ablation(rc, synth, torch)

@@ -242,7 +242,14 @@ struct RecheckArgs {
   double qt_x, qt_y, qr_x, qr_y, v_x, v_y;  // mean TX and RX positions and mean velocity (Doppler table)
   double height;            // antennas above the pixel plane, metres
   const float* fd_in;       // [n_pix] caller's f_doppler (bins) or nullptr
-  double* power;            // [cap][(2 half + 1)^2] scratch
+  // the pixels the listed windows need, each formed once: a bitmap in the
+  // mask's layout, the list of needed pixels (ascending), and per pixel its
+  // place in that list
+  unsigned long long* need;  // [n_rows][words_per_row]
+  int* plist;               // [cap * (2 half + 1)^2]
+  int* map;                 // [n_rows * n_cols]
+  int* n_need;
+  double* power;            // [cap * (2 half + 1)^2]: power of plist[i]
   unsigned long long* mask;
   int words_per_row;
   rc_detection* det_cell;

@@ -11,10 +11,14 @@
 // FFT (range64_kernel; a spectrum input is widened exactly), and the windows
 // come from the host in double.
 //
-// recheck_pixels_kernel: one workgroup per (listed cell, window offset), the
-// terms (chirp, channel) split over the 256 lanes and summed by a fixed tree,
-// so every recomputed power is deterministic.  recheck_decide_kernel: one lane
-// per listed cell.
+// Listed cells cluster around targets and their windows overlap, so every
+// pixel some window needs is formed once: need_mark_kernel marks them in a
+// bitmap, need_gather_kernel lists them in ascending order (and records each
+// one's place), recheck_pixels_kernel forms one listed pixel per workgroup —
+// the terms (chirp, channel) split over the 256 lanes and summed by a fixed
+// tree, so every recomputed power is deterministic — and
+// recheck_decide_kernel (one lane per listed cell) sums its window through
+// the map in a fixed order.
 #include <algorithm>
 
 #include "rc_kernels.hpp"
@@ -33,28 +37,96 @@ __device__ __forceinline__ double radial(double px, double py, double qx, double
   return *d > 0.0 ? (rx * vx + ry * vy) / *d : 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void recheck_pixels_kernel(RecheckArgs a) {
-  __shared__ double red_re[kThreads];
-  __shared__ double red_im[kThreads];
+// zeroes the need bitmap and the count of needed pixels
+__global__ __launch_bounds__(kThreads) void need_clear_kernel(RecheckArgs a) {
+  const int64_t n_words = (int64_t)a.n_rows * a.words_per_row;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * kThreads)
+    a.need[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_need = 0;
+}
+
+// marks the cell and the training pixels of every listed cell's window
+__global__ __launch_bounds__(kThreads) void need_mark_kernel(RecheckArgs a) {
   const int win = 2 * a.half + 1;
   const int n_off = win * win;
   const int count = min(*a.n_listed, a.cap);
   const int64_t n_work = (int64_t)count * n_off;
-  const int rows = a.n_chirps * a.n_ch;
-  for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+  for (int64_t wi = (int64_t)blockIdx.x * kThreads + threadIdx.x; wi < n_work; wi += (int64_t)gridDim.x * kThreads) {
     const int slot = (int)(wi / n_off);
     const int o = (int)(wi - (int64_t)slot * n_off);
     const int dr = o / win - a.half, dc = o % win - a.half;
-    const bool guard = (dr >= -a.guard && dr <= a.guard && dc >= -a.guard && dc <= a.guard) && (dr || dc);
-    if (guard) continue;  // uniform over the workgroup
+    if ((dr >= -a.guard && dr <= a.guard && dc >= -a.guard && dc <= a.guard) && (dr || dc)) continue;
     const int cell = a.listed[slot];
     const int r = cell / a.n_cols + dr, c = cell % a.n_cols + dc;  // inside: tested cells have full windows
-    const float2 pf = a.pix[(int64_t)r * a.n_cols + c];
+    atomicOr(a.need + (int64_t)r * a.words_per_row + c / 64, 1ull << (c % 64));
+  }
+}
+
+// lists the marked pixels in ascending order (one workgroup: sweeps of 256 x 8
+// words, a wave scan of the threads' counts and a scan of the four wave totals)
+constexpr int kGatherWords = 8;
+__global__ __launch_bounds__(kThreads) void need_gather_kernel(RecheckArgs a) {
+  __shared__ int wave_sum[kThreads / 64];
+  __shared__ int base_sh;
+  const int64_t n_words = (int64_t)a.n_rows * a.words_per_row;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base_sh = 0;
+  __syncthreads();
+  for (int64_t w0 = 0; w0 < n_words; w0 += (int64_t)kThreads * kGatherWords) {
+    const int64_t wt = w0 + (int64_t)threadIdx.x * kGatherWords;
+    unsigned long long word[kGatherWords];
+    int total = 0;
+#pragma unroll
+    for (int k = 0; k < kGatherWords; ++k) {
+      word[k] = wt + k < n_words ? a.need[wt + k] : 0ull;
+      total += __popcll(word[k]);
+    }
+    int incl = total;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wave_sum[wave] = incl;
+    __syncthreads();
+    int pos = base_sh + incl - total;
+    for (int k = 0; k < wave; ++k) pos += wave_sum[k];
+#pragma unroll
+    for (int k = 0; k < kGatherWords; ++k) {
+      unsigned long long bits = word[k];
+      if (!bits) continue;
+      const int64_t w = wt + k;
+      const int64_t r = w / a.words_per_row;
+      const int64_t cb = (w - r * a.words_per_row) * 64;
+      while (bits) {
+        const int b = __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        const int pixel = (int)(r * a.n_cols + cb + b);
+        a.plist[pos] = pixel;
+        a.map[pixel] = pos;
+        ++pos;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == kThreads - 1) base_sh = pos;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *a.n_need = base_sh;
+}
+
+__global__ __launch_bounds__(kThreads) void recheck_pixels_kernel(RecheckArgs a) {
+  __shared__ double red_re[kThreads];
+  __shared__ double red_im[kThreads];
+  const int n_need = *a.n_need;
+  const int rows = a.n_chirps * a.n_ch;
+  for (int wi = blockIdx.x; wi < n_need; wi += gridDim.x) {
+    const int pixel = a.plist[wi];
+    const float2 pf = a.pix[pixel];
     const double px = pf.x, py = pf.y;
     const double h2 = a.height * a.height;
     double fd = 0.0;
     if (a.fd_in) {
-      fd = (double)a.fd_in[(int64_t)r * a.n_cols + c];
+      fd = (double)a.fd_in[pixel];
     } else if (!a.exact) {
       double d0;
       fd = a.kd * (radial(px, py, a.qt_x, a.qt_y, a.v_x, a.v_y, h2, &d0) +
@@ -102,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void recheck_pixels_kernel(RecheckArgs a)
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) a.power[(int64_t)slot * n_off + o] = red_re[0] * red_re[0] + red_im[0] * red_im[0];
+    if (threadIdx.x == 0) a.power[wi] = red_re[0] * red_re[0] + red_im[0] * red_im[0];
     __syncthreads();
   }
 }
@@ -112,17 +184,16 @@ __global__ __launch_bounds__(kThreads) void recheck_decide_kernel(RecheckArgs a)
   const int n_off = win * win;
   const int count = min(*a.n_listed, a.cap);
   for (int slot = blockIdx.x * kThreads + threadIdx.x; slot < count; slot += gridDim.x * kThreads) {
-    const double* pw = a.power + (int64_t)slot * n_off;
+    const int cell = a.listed[slot];
+    const int r = cell / a.n_cols, c = cell % a.n_cols;
     double train = 0.0;
     for (int o = 0; o < n_off; ++o) {
       const int dr = o / win - a.half, dc = o % win - a.half;
       if (dr >= -a.guard && dr <= a.guard && dc >= -a.guard && dc <= a.guard) continue;
-      train += pw[o];
+      train += a.power[a.map[(int64_t)(r + dr) * a.n_cols + (c + dc)]];
     }
     const double thr = a.alpha_over_n * train;
-    const double p = pw[a.half * win + a.half];
-    const int cell = a.listed[slot];
-    const int r = cell / a.n_cols, c = cell % a.n_cols;
+    const double p = a.power[a.map[cell]];
     unsigned long long* word = a.mask + (int64_t)r * a.words_per_row + c / 64;
     const unsigned long long bit = 1ull << (c % 64);
     if (p > thr) {
@@ -222,9 +293,18 @@ hipError_t launch_recheck(const RecheckArgs& a, hipStream_t s) {
   if (a.half < 1 || a.half > 16 || a.guard < 0 || a.guard >= a.half || a.n_chirps < 1 || a.n_ch < 1 ||
       a.n_bins < 2 || a.n_cols < 1)
     return hipErrorInvalidValue;
+  if (!a.need || !a.plist || !a.map || !a.n_need || !a.power || a.words_per_row != (a.n_cols + 63) / 64)
+    return hipErrorInvalidValue;
   const int win = 2 * a.half + 1;
+  const int64_t n_words = (int64_t)a.n_rows * a.words_per_row;
+  const int64_t g0 = std::max<int64_t>(1, std::min<int64_t>((n_words + kThreads - 1) / kThreads, 1024));
+  hipLaunchKernelGGL(need_clear_kernel, dim3((unsigned)g0), dim3(kThreads), 0, s, a);
+  const int64_t g1 = std::min<int64_t>(((int64_t)a.cap * win * win + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(need_mark_kernel, dim3((unsigned)g1), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(need_gather_kernel, dim3(1), dim3(kThreads), 0, s, a);
+  // grid-stride over the needed pixels (count known on the device only)
   int64_t grid = (int64_t)a.cap * win * win;
-  if (grid > 8192) grid = 8192;  // grid-stride over the listed cells (count known on the device only)
+  if (grid > 8192) grid = 8192;
   hipLaunchKernelGGL(recheck_pixels_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

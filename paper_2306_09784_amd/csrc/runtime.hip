@@ -91,7 +91,11 @@ struct Slot {
   int64_t* det_count = nullptr;
   int* listed = nullptr;      // near-threshold cells for the double-precision recheck
   int* n_listed = nullptr;
-  double* rpower = nullptr;   // recomputed window powers of the listed cells
+  double* rpower = nullptr;   // recomputed powers of the pixels the listed windows need
+  unsigned long long* need = nullptr;  // bitmap of those pixels (mask layout)
+  int* plist = nullptr;       // those pixels, ascending
+  int* pmap = nullptr;        // pixel -> place in plist
+  int* n_need = nullptr;
   double2* spec64 = nullptr;  // beat spectrum in double for the recheck
   rc::RecheckArgs rk{};       // geometry part filled by prepare_frame
   // pinned host (staging: mapped and coherent, read by the upload kernel
@@ -158,10 +162,11 @@ size_t ring_bytes(const rc_plan_desc& d) {
 }
 
 struct SlotSizes {
-  size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out, listed, rpower, spec64;
+  size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out, listed, rpower, spec64, need,
+      plist, pmap;
   size_t total() const {
     return pairs + geo + fd + pixc + fbase + partials + image + mask + det_cell + det_out + listed + rpower +
-           spec64 + 64;
+           spec64 + need + plist + pmap + 64;
   }
 };
 
@@ -214,6 +219,10 @@ SlotSizes slot_sizes(const rc_plan_desc& d) {
   s.det_out = round_up((size_t)d.max_detections * sizeof(rc_detection));
   s.listed = round_up((size_t)d.max_rechecks * sizeof(int));
   s.rpower = round_up((size_t)d.max_rechecks * window_cells(d) * sizeof(double));
+  const bool rk = d.max_rechecks > 0;
+  s.need = rk ? round_up((size_t)d.n_pix_max * sizeof(unsigned long long)) : 0;
+  s.plist = rk ? round_up((size_t)d.max_rechecks * window_cells(d) * sizeof(int)) : 0;
+  s.pmap = rk ? round_up((size_t)d.n_pix_max * sizeof(int)) : 0;
   s.spec64 = d.max_rechecks > 0 ? round_up(rows * d.n_bins_max * sizeof(double2)) : 0;
   return s;
 }
@@ -677,6 +686,10 @@ rc_status finish_batch(Plan* p, const std::vector<Slot*>& slot, const rc_frame* 
       rk.guard = d.cfar_guard;
       rk.alpha_over_n = alpha / n_train;
       rk.power = s.rpower;
+      rk.need = s.need;
+      rk.plist = s.plist;
+      rk.map = s.pmap;
+      rk.n_need = s.n_need;
       rk.mask = s.mask;
       rk.words_per_row = wpr(i);
       rk.det_cell = s.det_cell;
@@ -808,9 +821,13 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     s.det_out = reinterpret_cast<rc_detection*>(take(sz.det_out));
     s.listed = sz.listed ? reinterpret_cast<int*>(take(sz.listed)) : nullptr;
     s.rpower = sz.rpower ? reinterpret_cast<double*>(take(sz.rpower)) : nullptr;
+    s.need = sz.need ? reinterpret_cast<unsigned long long*>(take(sz.need)) : nullptr;
+    s.plist = sz.plist ? reinterpret_cast<int*>(take(sz.plist)) : nullptr;
+    s.pmap = sz.pmap ? reinterpret_cast<int*>(take(sz.pmap)) : nullptr;
     s.spec64 = sz.spec64 ? reinterpret_cast<double2*>(take(sz.spec64)) : nullptr;
     s.det_count = reinterpret_cast<int64_t*>(take(64));
     s.n_listed = reinterpret_cast<int*>(s.det_count + 1);
+    s.n_need = s.n_listed + 1;
     e = hipHostMalloc(reinterpret_cast<void**>(&s.staging), geo_bytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) {
       void* dev = nullptr;
