@@ -179,12 +179,12 @@ size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Pixel-blocks of partial images a slot may need: a frame of W waves (64
 // lanes each, covering at least its n_pix pixels) is split into
-// n_kb = min(16, ceil(32768 / W)) chirp blocks, so
-// n_kb * n_pix <= min(16 n_pix, (32768 / W + 1) n_pix) <= min(16 n_pix, 2^21 + n_pix);
+// n_kb = min(16, ceil(T 8192 / W)) chirp blocks (T generations of waves), so
+// n_kb * n_pix <= min(16 n_pix, (T 8192 / W + 1) n_pix) <= min(16 n_pix, T 2^19 + n_pix);
 // a continuous-SAR sub-aperture has three such images per block (Hann window).
 int64_t partial_capacity(const rc_plan_desc& d) {
   const int64_t planes = d.sliding_sensors > 0 && d.sar_window == RC_WIN_HANN ? 3 : 1;
-  return planes * std::min<int64_t>(16 * d.n_pix_max, (int64_t(1) << 21) + d.n_pix_max);
+  return planes * std::min<int64_t>(16 * d.n_pix_max, (int64_t)rc::kBpTargetGenerations * (1 << 19) + d.n_pix_max);
 }
 
 // staging/device geometry region: rowq[rows] and grpq[rows] float4; with the
