@@ -385,21 +385,22 @@ void bp_tiles(int n_rows, int n_cols, int* tiles_x, int* n_tiles) {
   }
 }
 
-int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps, int n_ch) {
+int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps, int n_ch, int planes) {
   // 256 CUs x 4 SIMDs x 8 waves = 8192 resident waves.  Aim at ten
   // generations of waves: the ragged end of the launch then idles a small
   // share of it (measured, a lone frame's time stops falling from about ten
   // generations on).  But each block also adds a wave's fixed work (pixel
-  // tables, range proof, stores) and a partial image to write and reduce,
-  // which frames batched together pay without needing the extra waves: so at
-  // least kBpMinBlockRows rows (chirps x channels) per block, unless fewer
-  // would leave a lone frame short of one generation.  At most 16 blocks and
-  // at least one chirp per block.
+  // tables, range proof, stores) and `planes` partial images to write and
+  // reduce, which frames batched together, or streamed two at a time, pay
+  // without needing the extra waves: so at least planes x kBpMinBlockRows rows
+  // (chirps x channels) per block, unless fewer blocks would leave a lone
+  // frame short of one generation.  At most 16 blocks and at least one chirp
+  // per block.
   int tx, nt;
   bp_tiles((int)n_rows, (int)n_cols, &tx, &nt);
   const int64_t waves = (int64_t)nt * (kThreads / 64);
   int64_t k = (kBpTargetGenerations * 8192 + waves - 1) / waves;
-  const int64_t by_rows = (int64_t)n_chirps * n_ch / kBpMinBlockRows;
+  const int64_t by_rows = (int64_t)n_chirps * n_ch / ((int64_t)planes * kBpMinBlockRows);
   const int64_t fill = (8192 + waves - 1) / waves;
   if (k > by_rows) k = by_rows > fill ? by_rows : fill;
   if (k > 16) k = 16;

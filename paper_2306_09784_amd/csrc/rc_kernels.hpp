@@ -163,14 +163,15 @@ struct BpBatch {
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s);
 
 // Chirp blocks a frame of n_rows x n_cols pixels, n_chirps chirps and n_ch
-// channels is split into, so that a launch of it alone has enough waves to
-// fill the GPU: about kBpTargetGenerations x 8192 waves (the resident waves of
-// the chip), at most 16 blocks and at least kBpMinBlockRows rows (chirps x
-// channels) per block where one generation stays filled, so k blocks of W
-// waves each satisfy k <= min(16, ceil(T 8192 / W)).
+// channels, whose blocks write `planes` partial images each, is split into,
+// so that a launch of it alone has enough waves to fill the GPU: about
+// kBpTargetGenerations x 8192 waves (the resident waves of the chip), at most
+// 16 blocks and at least planes x kBpMinBlockRows rows (chirps x channels) per
+// block where one generation stays filled, so k blocks of W waves each
+// satisfy k <= min(16, ceil(T 8192 / W)).
 constexpr int kBpTargetGenerations = 10;
 constexpr int kBpMinBlockRows = 512;
-int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps, int n_ch);
+int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps, int n_ch, int planes);
 // Number of work items (workgroups) of one chirp block of a frame.
 void bp_tiles(int n_rows, int n_cols, int* tiles_x, int* n_tiles);
 

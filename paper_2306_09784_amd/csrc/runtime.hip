@@ -297,9 +297,10 @@ void free_plan(Plan* p) {
 // Chirp blocks of a frame's back-projection; a sub-aperture's partial images
 // have `planes` planes each and must fit the slot's partial buffer.
 int frame_chirp_blocks(const Plan* p, const rc_frame& f) {
-  int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps, f.n_channels);
+  const int planes = f.sliding != RC_SLIDE_OFF ? p->planes : 1;
+  int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps, f.n_channels, planes);
   if (f.sliding != RC_SLIDE_OFF && n_kb > 1) {
-    const int64_t per = (int64_t)p->planes * f.n_rows * f.n_cols;
+    const int64_t per = (int64_t)planes * f.n_rows * f.n_cols;
     const int64_t fit = partial_capacity(p->d) / per;
     if (fit < n_kb) n_kb = fit < 2 ? 1 : (int)fit;
   }
