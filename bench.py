@@ -237,7 +237,7 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
     return res
 
 
-def paper_config(rc, synth, torch, steps):
+def paper_config(rc, synth, torch, steps, warmup):
     """The paper's combined setting (Sec. IV, Tab. II rows 7-8): 1024 chirps x
     8 RX, 30 m x 30 m scene on the polar grid of Sec. III-E, synthetic data."""
     cfg = synth.CONFIGS["paper-polar"]
@@ -248,12 +248,12 @@ def paper_config(rc, synth, torch, steps):
     pix = rc.grid_polar(g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"])
     x0, x1, y0, y1 = cfg.box
     in_box = int(np.sum((pix[:, 0] >= x0) & (pix[:, 0] <= x1) & (pix[:, 1] >= y0) & (pix[:, 1] <= y1)))
-    # one stream: frames this short (four or five generations of waves)
-    # would overlap for most of their back-projection on two streams, and two
-    # frames' tables in each XCD's L2 cost more than the overlap gains
-    run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, steps, 1,
-                        want_image=True, n_streams=1)
-    one = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, 10, 1, depth=1)
+    # frames this short (1.2 ms of back-projection) take many frames for the
+    # GPU's clock to settle: at least 20 untimed and 100 timed ones
+    run = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, max(100, steps),
+                        max(20, warmup), want_image=True)
+    one = time_pipeline(rc, synth, torch, frame, pix, g["nth"], g["nr"], rc.RC_PREC_FP32, 20, max(20, warmup),
+                        depth=1)
     n_pix = g["nth"] * g["nr"]
     terms = float(n_pix) * cfg.n_chirps * cfg.n_channels
     bp_ms = float(one["stages"][:, 2].mean())
@@ -451,7 +451,7 @@ def _target_gain_db(img, pix, targets, ref_img, ref_pix, rad=0.06):
     return float(np.mean(out)) if out else None
 
 
-def ablation(rc, synth, torch, steps=3):
+def ablation(rc, synth, torch, steps=5, warmup=5):
     """The measures of the paper's Tab. II on one synthetic frame of its
     reference setting (1024 chirps x 16 RX, 30 m x 30 m): Alg. 1 on the 2.5 cm
     Cartesian grid (reference), then the Doppler table (Alg. 2), the polar grid
@@ -479,7 +479,7 @@ def ablation(rc, synth, torch, steps=3):
              "combined": (2.9, 2.4)}
     out, ref_ms, ref_img = {}, None, None
     for name, (fr, pix, nr, nc, dop) in runs.items():
-        run = time_pipeline(rc, synth, torch, fr, pix, nr, nc, rc.RC_PREC_FP32, steps, 1, doppler=dop,
+        run = time_pipeline(rc, synth, torch, fr, pix, nr, nc, rc.RC_PREC_FP32, steps, warmup, doppler=dop,
                             want_image=True, depth=1)
         bp_ms = float(run["stages"][:, 2].mean())
         ref_ms = ref_ms or bp_ms
@@ -610,8 +610,8 @@ def progress(msg: str) -> None:
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="plain-large")
     ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
                     help="HIP streams the main workload's frames alternate over (1 for profiling: kernels of "
@@ -672,7 +672,7 @@ def main(argv=None):
                              rc.RC_PREC_FP32, args.steps, args.warmup, n_streams=args.streams)
     # frame latency alone (one frame in flight)
     lat_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                            rc.RC_PREC_FP32, 10, 1, depth=1)
+                            rc.RC_PREC_FP32, 20, args.warmup, depth=1)
     # per-stage device times (and the roofline) from the single-frame run: with
     # two frames on two streams, kernels of different frames overlap and a
     # launch's duration no longer measures the launch alone
@@ -741,16 +741,16 @@ def main(argv=None):
     if not args.main_only:
         # the same frame with the split-phase (high-accuracy) form
         sp = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                           rc.RC_PREC_FP32_SPLIT, max(5, args.steps // 2), 1)
+                           rc.RC_PREC_FP32_SPLIT, max(5, args.steps // 2), args.warmup)
         sp1 = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                            rc.RC_PREC_FP32_SPLIT, 5, 1, depth=1)
+                            rc.RC_PREC_FP32_SPLIT, 10, args.warmup, depth=1)
         out["split_phase_form"] = {
             "frames_per_s": sp["fps"], "backprojection_ms": float(sp1["stages"][:, 2].mean()),
             "p99_ms": 1e3 * float(np.percentile(sp1["lat"], 99))}
         progress("split-phase form done")
         # the same frame with the double-precision recheck of near-threshold cells
-        rk = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_PREC_FP32, 5, 1,
-                           depth=1, plan_kw=dict(max_rechecks=4096))
+        rk = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_PREC_FP32, 5,
+                           args.warmup, depth=1, plan_kw=dict(max_rechecks=4096))
         flags = rk["detections"]["flags"]
         out["fp64_recheck"] = {
             "max_rechecks": 4096, "cfar_margin_rel": 0.03,
@@ -762,7 +762,7 @@ def main(argv=None):
             "detections": int(len(flags)), "decided_in_fp64": int(((flags & rc.RC_DET_RECHECKED) != 0).sum()),
             "still_near_threshold": int(((flags & rc.RC_DET_NEAR_THRESHOLD) != 0).sum())}
         progress("recheck done")
-        out["paper_config"] = paper_config(rc, synth, torch, max(5, args.steps // 2))
+        out["paper_config"] = paper_config(rc, synth, torch, args.steps, args.warmup)
         progress("paper configuration done")
         out["tab2_ablation"] = ablation(rc, synth, torch)
         progress("Tab. II ablation done")
