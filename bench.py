@@ -206,12 +206,14 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
                                     height=cfg.height)
             plan.process([fr], streams[fid % n_streams])
 
-        for i in range(warmup):
-            submit(i)
-            plan.detections(i)
-            plan.release(i)
-        torch.cuda.synchronize()
+        # the collector runs before the warm-up, not between it and the timed
+        # frames: a pause there lets the GPU's clock drop again
         with no_gc():
+            for i in range(warmup):
+                submit(i)
+                plan.detections(i)
+                plan.release(i)
+            torch.cuda.synchronize()
             t_start = time.perf_counter()
             t_sub = {}
             queue = []
@@ -379,17 +381,19 @@ def continuous_sar(rc, synth, torch, main_fps, drive, sub_cycles=128, K=4, depth
                                        rc.RC_SLIDE_START if j == 0 else rc.RC_SLIDE_NEXT))
             plan.process([f], streams[j % 2])
 
-        for n, j in enumerate(list(range(n_sub)) + list(range(K - 1))):
-            # an untimed pass over the stream, one sub-aperture at a time (its
-            # full apertures give the stage times: kernels of concurrent
-            # sub-apertures would overlap), then the restarted stream's
-            # first, partial apertures
-            submit(j)
-            if K - 1 <= n < n_sub:
-                stages.append(plan.stage_times(j))
-            plan.release(j)
-        torch.cuda.synchronize()
+        # the collector runs before the untimed pass, not between it and the
+        # timed apertures (a pause there lets the GPU's clock drop again)
         with no_gc():
+            for n, j in enumerate(list(range(n_sub)) + list(range(K - 1))):
+                # an untimed pass over the stream, one sub-aperture at a time
+                # (its full apertures give the stage times: kernels of
+                # concurrent sub-apertures would overlap), then the restarted
+                # stream's first, partial apertures
+                submit(j)
+                if K - 1 <= n < n_sub:
+                    stages.append(plan.stage_times(j))
+                plan.release(j)
+            torch.cuda.synchronize()
             t_start = time.perf_counter()
             t_sub, queue = {}, []
             for j in range(K - 1, n_sub):
@@ -544,12 +548,12 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=F
     srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch), n_streams=2, resident=resident)
     try:
         order = [sensors[i % len(sensors)] for i in range(n_frames)]
-        # warm-up batch
-        srv.submit([(10**6 + i, order[i], time.perf_counter()) for i in range(min(batch, n_frames))])
-        srv.harvest(block=True)
-        srv.results.clear()
-        torch.cuda.synchronize()
         with no_gc():
+            # warm-up batch (after the collector ran: no pause before the timed batches)
+            srv.submit([(10**6 + i, order[i], time.perf_counter()) for i in range(min(batch, n_frames))])
+            srv.harvest(block=True)
+            srv.results.clear()
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             fid = 1
             for b0 in range(0, n_frames, batch):
