@@ -180,6 +180,32 @@ def test_bp_parity_spectrum_input(rc, torch, n_tx, n_rx, n_chirps, precision):
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("n_rx,n_chirps,nx,ny,sampled", [(4, 100, 45, 37, False), (8, 333, 512, 256, True)],
+                         ids=["16_blocks_of_6_or_7", "5_blocks_of_66_or_67"])
+def test_bp_parity_uneven_chirp_blocks(rc, torch, n_rx, n_chirps, nx, ny, sampled, precision):
+    """Chirp counts that the frame's chirp blocks do not divide evenly.  A
+    37 x 45 lattice (36 waves) with 100 chirps x 4 channels is split into 16
+    blocks (one generation of resident waves needs more than 16) of 6 or 7
+    chirps; a 256 x 512 lattice (2048 waves) with 333 chirps x 8 channels into
+    5 blocks (at least 512 of its 2664 rows each; one generation needs only 4)
+    of 66 or 67 chirps, its oracle on sampled pixels."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="uneven", n_samples=64, n_chirps=n_chirps,
+                              n_tx=1, n_rx=n_rx, nx=nx, ny=ny, box=(-6.0, 6.0, 1.5, 9.0), n_targets=1,
+                              noise=False, seed=31 + n_chirps)
+    fr = synth.make_frame(cfg)
+    rng = np.random.default_rng(300 + n_chirps)
+    spec = synth.random_spectrum(rng, (cfg.n_chirps, cfg.n_channels, fr.n_bins))
+    with rc.Plan(SC.plan_config(rc, [fr], precision=precision)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, spectrum=spec)
+    idx = None
+    if sampled:
+        idx = np.unique(np.concatenate([rng.integers(0, fr.n_rows * fr.n_cols, 400),
+                                        np.argsort(-np.abs(out["image"]))[:50]]))
+    ora = SC.run_oracle(fr, spectrum=spec, pix_index=idx, cfar=None)
+    _check_image(f"uneven_blocks_m{n_chirps}", fr, out["image"], ora, precision, pix_index=idx)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
 def test_bp_parity_indices_out_of_range(rc, torch, precision):
     """Too few kept bins: many terms fall outside [0, n_bins - 1] and must
     contribute zero (range-tested path), others stay in range."""
