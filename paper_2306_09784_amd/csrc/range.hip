@@ -14,14 +14,16 @@
 // layout that back-projection gathers with one 16-byte load per term, with
 // the chirp window w_sar[m] folded in.  Pass p of radix R at stride Ns
 // multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (loaded from the
-// frame's n_fft-point full-circle twiddle table, which the host evaluates in
-// double) and writes output r to (b / Ns) Ns R + (b mod Ns) + r Ns.  When every
+// hardware sine and cosine, which take their argument in turns: the argument
+// (b mod Ns) r / (Ns R) is exact in single precision, so each twiddle carries
+// only the unit's own rounding, about 1e-7, and costs no memory access) and
+// writes output r to (b / Ns) Ns R + (b mod Ns) + r Ns.  When every
 // row of a launch has at most n_fft / 2 samples (zero padding by two or more,
 // the usual case), the upper half of every first-pass butterfly's inputs is
 // zero at compile time: neither loaded nor computed.  LDS rows are padded by one element
 // per 16, which keeps the stride-16 writes of the first passes free of bank
-// conflicts.  Rows shorter than 16 x 64 samples share a workgroup.  Samples,
-// the range window and twiddles are read through buffer descriptors: the
+// conflicts.  Rows shorter than 16 x 64 samples share a workgroup.  Samples
+// and the range window are read through buffer descriptors: the
 // zero padding and the rows past the frame read past the descriptor's range,
 // which returns zeros without a branch.
 #include "rc_kernels.hpp"
@@ -113,7 +115,6 @@ struct Fft {
 struct RowIo {
   __amdgpu_buffer_rsrc_t raw;   // the frame's samples
   __amdgpu_buffer_rsrc_t win;   // w_range; an index past n_s reads 0
-  __amdgpu_buffer_rsrc_t tw;    // twiddle table
   unsigned row_off;             // byte offset of this lane's row in raw
   bool live;
 };
@@ -128,17 +129,15 @@ __device__ __forceinline__ void fft_pass(const RangeArgs& a, const RowIo& io, fl
   float2 v[E];
   float2 w[E];
   if constexpr (NS > 1) {
-    constexpr int lg = __builtin_ctz(NS * R);
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int b = j + T * u;
-      // byte offset of W_{NS R}^{(b mod NS) r} in the n_fft-point table, stepped in r
-      const unsigned step = (unsigned)((b & (NS - 1)) << (LOG2N - lg)) * 8u;
-      unsigned off = step;
+      // W_{NS R}^{(b mod NS) r} = exp(-2 pi i t), t = (b mod NS) r / (NS R) turns
+      const float q = (float)(b & (NS - 1)) * (1.0f / (float)(NS * R));
 #pragma unroll
-      for (int r = 1; r < R; ++r, off += step) {
-        const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(io.tw, off, 0, 0);
-        w[u * R + r] = make_float2(__uint_as_float(t.x), __uint_as_float(t.y));
+      for (int r = 1; r < R; ++r) {
+        const float t = q * (float)r;
+        w[u * R + r] = make_float2(__builtin_amdgcn_cosf(t), -__builtin_amdgcn_sinf(t));
       }
     }
   }
@@ -211,7 +210,6 @@ __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeMulti m) 
   io.row_off = (unsigned)(row * a.n_s) * 8u;
   io.live = live;
   io.win = __builtin_amdgcn_make_buffer_rsrc((void*)a.w_range, (short)0, a.n_s * 4, kRsrcWord3);
-  io.tw = __builtin_amdgcn_make_buffer_rsrc((void*)a.twiddle, (short)0, 8 << LOG2N, kRsrcWord3);
 
   if constexpr (LOG2N < 4) {
     fft_pass<LOG2N, F::N, 1, true, true, HALF>(a, io, buf, j);
@@ -279,8 +277,7 @@ hipError_t launch_range_compress(const RangeMulti& m, hipStream_t s) {
     const RangeArgs& a = m.f[i];
     if (a.rows < 0 || a.n_fft < 4 || (a.n_fft & (a.n_fft - 1)) || (1 << a.log2n) != a.n_fft ||
         a.n_fft > 4096 || a.log2n != log2n || a.n_s < 1 || a.n_s > a.n_fft || a.n_bins < 1 ||
-        a.n_bins > a.n_fft || a.n_ch < 1 || a.tw_log2 != a.log2n || !a.twiddle ||
-        a.rows * a.n_s * 8 >= (int64_t(1) << 31))
+        a.n_bins > a.n_fft || a.n_ch < 1 || a.rows * a.n_s * 8 >= (int64_t(1) << 31))
       return hipErrorInvalidValue;
   }
   switch (log2n) {

@@ -49,8 +49,6 @@ struct RangeArgs {
   const float2* raw;      // [rows][n_s]
   const float* w_range;   // [n_s]
   const float* w_sar;     // [n_chirps]
-  const float2* twiddle;  // [n_fft], exp(-2 pi i k / n_fft)
-  int tw_log2;            // log2(n_fft)
   float4* pairs;          // [rows][n_bins]
   float2* spectrum;       // [rows][n_bins] or nullptr
   int64_t rows;

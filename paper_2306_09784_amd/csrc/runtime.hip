@@ -140,10 +140,10 @@ struct Slide {
 struct Plan {
   rc_plan_desc d;
   int device = 0;
-  // single-precision twiddles exp(-2 pi i k / N) for every DFT length
-  // N = 4 .. n_fft_max, the table of length N at offset N - 4
-  float2* twiddle = nullptr;
-  double2* twiddle64 = nullptr;  // with the recheck on
+  // with the recheck on: double twiddles exp(-2 pi i k / n_fft_max) over the
+  // half circle (single-precision range compression takes its twiddles from
+  // the hardware sine and cosine)
+  double2* twiddle64 = nullptr;
   int tw_log2 = 0;
   size_t geo_floats = 0;  // floats of the staging/rowgeo region
   std::vector<Slot> slots;
@@ -289,7 +289,6 @@ void free_plan(Plan* p) {
   for (Sensor& s : p->sensors)
     if (s.done) (void)hipEventDestroy(s.done);
   if (p->ring) (void)hipFree(p->ring);
-  if (p->twiddle) (void)hipFree(p->twiddle);
   if (p->twiddle64) (void)hipFree(p->twiddle64);
   delete p;
 }
@@ -526,8 +525,6 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
     ra.raw = static_cast<const float2*>(f.data);
     ra.w_range = d_wrange;
     ra.w_sar = d_wsar;
-    ra.twiddle = p->twiddle + (f.n_fft - 4);
-    ra.tw_log2 = ilog2(f.n_fft);
     ra.pairs = s.pairs;
     ra.spectrum = static_cast<float2*>(f.spectrum_out);
     ra.rows = rows;
@@ -737,9 +734,8 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
   if (st != RC_OK) return st;
   const SlotSizes sz = slot_sizes(*desc);
   const size_t per_slot = sz.total();
-  const size_t tw_bytes = (2 * (size_t)desc->n_fft_max - 4) * sizeof(float2);
   const size_t tw64_bytes = desc->max_rechecks > 0 ? (size_t)desc->n_fft_max / 2 * sizeof(double2) : 0;
-  const size_t need = per_slot * desc->max_frames_in_flight + tw_bytes + tw64_bytes + ring_bytes(*desc);
+  const size_t need = per_slot * desc->max_frames_in_flight + tw64_bytes + ring_bytes(*desc);
   if (desc->hbm_budget_bytes > 0 && need > (size_t)desc->hbm_budget_bytes)
     return fail(RC_ENOMEM, "plan needs %zu bytes of device memory, budget is %lld", need,
                 (long long)desc->hbm_budget_bytes);
@@ -752,28 +748,16 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     delete p;
     return fail(RC_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
   }
-  // twiddles evaluated in double: single precision over the full circle of
-  // every DFT length N = 4 .. n_fft_max (length N at offset N - 4), double
-  // over the half circle of n_fft_max (for the recheck)
+  // double twiddles over the half circle of n_fft_max (for the recheck)
   p->tw_log2 = ilog2(desc->n_fft_max);
-  {
-    std::vector<float2> tw(2 * (size_t)desc->n_fft_max - 4);
-    for (int64_t n = 4; n <= desc->n_fft_max; n *= 2)
-      for (int64_t k = 0; k < n; ++k) {
-        const double a = -2.0 * kPi * (double)k / (double)n;
-        tw[n - 4 + k] = make_float2((float)std::cos(a), (float)std::sin(a));
-      }
-    e = hipMalloc(&p->twiddle, tw_bytes);
-    if (e == hipSuccess) e = hipMemcpy(p->twiddle, tw.data(), tw_bytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess && desc->max_rechecks > 0) {
-      std::vector<double2> tw64(desc->n_fft_max / 2);
-      for (size_t k = 0; k < tw64.size(); ++k) {
-        const double a = -2.0 * kPi * (double)k / desc->n_fft_max;
-        tw64[k] = make_double2(std::cos(a), std::sin(a));
-      }
-      e = hipMalloc(&p->twiddle64, tw64_bytes);
-      if (e == hipSuccess) e = hipMemcpy(p->twiddle64, tw64.data(), tw64_bytes, hipMemcpyHostToDevice);
+  if (desc->max_rechecks > 0) {
+    std::vector<double2> tw64(desc->n_fft_max / 2);
+    for (size_t k = 0; k < tw64.size(); ++k) {
+      const double a = -2.0 * kPi * (double)k / desc->n_fft_max;
+      tw64[k] = make_double2(std::cos(a), std::sin(a));
     }
+    e = hipMalloc(&p->twiddle64, tw64_bytes);
+    if (e == hipSuccess) e = hipMemcpy(p->twiddle64, tw64.data(), tw64_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       free_plan(p);
       return fail(e == hipErrorOutOfMemory ? RC_ENOMEM : RC_EHIP, "twiddle table: %s", hipGetErrorString(e));
