@@ -52,12 +52,13 @@ def alg2_cost(chg: int):
     term, plus the TX distance with the pixel's correction term (7) once per
     group of chg channels that share a TX position.
     Slots: 11 add/mul/FMA (squared distance 3, path sum 1, index 1,
-    interpolation 2, multiply-accumulate 4), 3 half-rate (index conversion
-    and fraction, byte offset) and 3 transcendentals (sqrt, sin, cos) per
-    term, plus 4 add/FMA and 1 sqrt per TX distance.
+    interpolation 2, multiply-accumulate 4), 2 half-rate (index conversion
+    and fraction; the table load takes the bin index itself, which the
+    buffer descriptor's 16-byte stride scales) and 3 transcendentals (sqrt,
+    sin, cos) per term, plus 4 add/FMA and 1 sqrt per TX distance.
     """
     flops = 24.0 + 7.0 / chg
-    slots = 11.0 + 3 * HALF_SLOTS + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
+    slots = 11.0 + 2 * HALF_SLOTS + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
     return flops, slots
 
 

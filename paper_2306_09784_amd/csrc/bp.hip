@@ -56,6 +56,14 @@ constexpr int kThreads = 256;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 
+// Indexed ("structured") buffer load of one 16-byte record: the hardware
+// forms base + vindex x stride from the descriptor's stride, so the caller
+// passes the record index instead of a byte offset.  Declared by its LLVM
+// intrinsic name (the compiler has no builtin for it; the backend emits
+// buffer_load_dwordx4 ... idxen and tracks the load like any other).
+__device__ u32x4 struct_buffer_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
+                                         int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+
 // Per-form geometry of one term.  Plain (Alg. 2): d = sqrt(|P|^2 + |q|^2 -
 // 2 P.q) from the per-row uniforms (-2 q, |q|^2) and the pixel's |P|^2 split
 // into a float and a correction.  Split-phase: d = R + delta with
@@ -170,9 +178,19 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
         st.phi[j] = __builtin_amdgcn_fractf(f);
       }
       st.turn[j] = turn;
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(tab + (size_t)(r + j) * a.n_bins), (short)0, row_bytes, kRsrcWord3);
-      st.e[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
+      if (CHECKED) {
+        // i = -1 reads past the descriptor's range: zeros, no access
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(tab + (size_t)(r + j) * a.n_bins), (short)0, row_bytes, kRsrcWord3);
+        st.e[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)i * 16u, 0, 0);
+      } else {
+        // 0 <= i <= n_bins - 1 by the wave's range proof: the record index
+        // goes to the load, which scales it by the 16-byte stride (no shift
+        // per term)
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(tab + (size_t)(r + j) * a.n_bins), (short)16, row_bytes, kRsrcWord3);
+        st.e[j] = struct_buffer_load_b128(rs, i, 0, 0, 0);
+      }
     }
   };
   // PAR selects the accumulator pair of a single-row stage
