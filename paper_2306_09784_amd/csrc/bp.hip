@@ -404,7 +404,9 @@ void bp_tiles(int n_rows, int n_cols, int* tiles_x, int* n_tiles) {
 }
 
 int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps, int n_ch, int planes) {
-  // 256 CUs x 4 SIMDs x 8 waves = 8192 resident waves.  Aim at ten
+  // 256 CUs x 4 SIMDs x 8 waves = 8192 wave slots (the plain kernel's 65
+  // VGPRs leave 7 per SIMD resident: 7168; the split below is measured, not
+  // exact in that unit).  Aim at ten
   // generations of waves: the ragged end of the launch then idles a small
   // share of it (measured, a lone frame's time stops falling from about ten
   // generations on).  But each block also adds a wave's fixed work (pixel
