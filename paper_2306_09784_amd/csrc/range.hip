@@ -13,7 +13,7 @@
 // n_bins bins that are written, directly in the interleaved (value, slope)
 // layout that back-projection gathers with one 16-byte load per term, with
 // the chirp window w_sar[m] folded in.  Pass p of radix R at stride Ns
-// multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (loaded from the
+// multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (evaluated by the
 // hardware sine and cosine, which take their argument in turns: the argument
 // (b mod Ns) r / (Ns R) is exact in single precision, so each twiddle carries
 // only the unit's own rounding, about 1e-7, and costs no memory access) and
