@@ -636,7 +636,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus}: this build runs one frame pipeline on one GPU; "
+        print(f"bench.py: --gpus {args.gpus}: the benchmark runs one frame pipeline on one GPU; "
               "frames and sensors shard across GPUs without communication, but only N=1 is measured",
               file=sys.stderr)
         return 2

@@ -1,0 +1,60 @@
+"""Host logic of bench.py (CPU only): the issue-slot model behind the ALU
+roofline, the rule that measured HBM traffic is reported only for the kernel
+sources it was measured on, and the refusal of more than one GPU before any
+device work."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("chg", [1, 2, 4, 8, 16])
+def test_alg2_cost_model(chg):
+    """Flops: 24 per term plus the TX distance (7) shared by chg channels.
+    Issue slots: 11 full-rate + 2 half-rate (x2) + 3 transcendental (x4) per
+    term, plus 4 full-rate + 1 sqrt per TX distance."""
+    flops, slots = bench.alg2_cost(chg)
+    assert flops == pytest.approx(24.0 + 7.0 / chg)
+    assert slots == pytest.approx(11 + 2 * 2 + 3 * 4 + (4 + 4) / chg)
+    # the ceiling in TFLOP/s is the lane-instruction rate spread over the slots
+    peak = bench.VALU_LANE_OPS / slots * flops / 1e12
+    assert peak < 157.3  # below the published FP32 vector peak (FMA = 2 flops)
+
+
+def test_chg4_ceiling():
+    """256 CUs x 128 lanes x 2.4 GHz / 29 slots = 2.71e12 terms/s at chg 4."""
+    _, slots = bench.alg2_cost(4)
+    assert slots == 29.0
+    assert bench.VALU_LANE_OPS / slots == pytest.approx(2.7118e12, rel=1e-4)
+
+
+def test_traffic_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
+    """The committed counter summary matches the committed kernel sources; a
+    summary taken on other sources (a different hash) gives no traffic."""
+    t = bench.measured_traffic("plain-large")
+    assert t is not None and 1e8 < t < 1e10
+    fake = tmp_path / "repo"
+    shutil.copytree(os.path.join(ROOT, "profiles"), fake / "profiles")
+    shutil.copytree(os.path.join(ROOT, "paper_2306_09784_amd", "csrc"), fake / "paper_2306_09784_amd" / "csrc")
+    monkeypatch.setattr(bench, "ROOT", str(fake))
+    assert bench.measured_traffic("plain-large") == pytest.approx(t)
+    src = fake / "paper_2306_09784_amd" / "csrc" / "bp.hip"
+    src.write_text(src.read_text() + "\n// changed\n")
+    assert bench.measured_traffic("plain-large") is None
+    assert bench.measured_traffic("no-such-workload") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    """--gpus 2 ends with exit status 2 and a message, before any GPU work."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
