@@ -36,6 +36,7 @@ PLAIN_TOL = 5e-3
 SPLIT_TOL = 2e-4
 BP_FLOOR = 1e-5
 PLAIN, SPLIT = 0, 1
+R = synth.RADAR
 PRECISIONS = [pytest.param(PLAIN, id="fp32"), pytest.param(SPLIT, id="split")]
 
 
@@ -331,6 +332,33 @@ def test_plain_large_sampled_pixels(rc, torch, precision):
                                     np.argsort(-np.abs(out["image"]))[:50]]))
     ora = SC.run_oracle(fr, spectrum=s, pix_index=idx, cfar=None)
     _check_image("image_large_sampled", fr, out["image"], ora, precision, pix_index=idx)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_paper_configuration_sampled_pixels(rc, torch, precision):
+    """The paper's combined setting (Sec. IV, Tab. II rows 7-8) at full size in
+    the benchmark's launch configuration: 1024 samples x 1024 chirps x 8 RX on
+    the 557 x 520 polar lattice of Sec. III-E (sixteen chirp blocks); oracle on
+    sampled pixels and the image's strongest ones."""
+    cfg = synth.CONFIGS["paper-polar"]
+    fr = synth.make_frame(cfg, device="cuda")
+    q = np.concatenate([fr.q_tx.reshape(-1, 2), fr.q_rx.reshape(-1, 2)])
+    g = rc.grid_polar_params(R, cfg.box, (float(q[:, 0].mean()), float(q[:, 1].mean())), float(np.ptp(q[:, 0])))
+    pol = rc.grid_polar(g["ox"], g["oy"], g["r0"], g["dr"], g["nr"], g["th0"], g["dth"], g["nth"])
+    fr = dataclasses.replace(fr, pix=pol, n_rows=g["nth"], n_cols=g["nr"])
+    assert (fr.n_rows, fr.n_cols) == (557, 520)
+    with rc.Plan(SC.plan_config(rc, [fr], precision=precision)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch, want_spectrum=True)
+    s = O.range_compress(fr.raw, O.window("hann", cfg.n_samples), fr.n_fft, fr.n_bins)
+    rel_l2 = float(np.linalg.norm(out["spectrum"] - s) / np.linalg.norm(s))
+    _report("range_paper", rel_l2=rel_l2)
+    assert rel_l2 <= SPEC_TOL
+    rng = np.random.default_rng(78)
+    idx = np.unique(np.concatenate([rng.integers(0, fr.n_rows * fr.n_cols, 400),
+                                    np.argsort(-np.abs(out["image"]))[:50]]))
+    ora = SC.run_oracle(fr, spectrum=s, pix_index=idx, cfar=None)
+    _check_image("image_paper_sampled", fr, out["image"], ora, precision, pix_index=idx)
 
 
 # ---------------------------------------------------------------------------
