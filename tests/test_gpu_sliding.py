@@ -174,6 +174,43 @@ def test_sliding_stream_parity(rc, torch, precision, exact):
     assert worst_rel <= (SPLIT_TOL if precision == SPLIT else PLAIN_TOL)
 
 
+@pytest.mark.slow
+def test_sliding_full_size_sampled_pixels(rc, torch):
+    """The benchmark's continuous-SAR workload at full size: the plain-large
+    sensor (1024 samples, 4 TX x 4 RX, 1201 x 1201 grid) driving on for five
+    sub-apertures of 128 TDM cycles, apertures of the last K = 4 (512 cycles,
+    Hann over the aperture), each sub-aperture one chirp block; the two full
+    apertures and a partial one against the oracle on sampled pixels and the
+    image's strongest ones."""
+    K, S, nb = 4, 128, 5
+    cfg = dataclasses.replace(synth.CONFIGS["plain-large"], name="plain-large-stream", n_chirps=nb * S)
+    fr = synth.make_frame(cfg, device="cuda")
+    blocks = []
+    for j in range(nb):
+        sl = slice(j * S, (j + 1) * S)
+        blocks.append(dict(raw=np.ascontiguousarray(fr.raw[sl]), q_tx=np.ascontiguousarray(fr.q_tx[sl]),
+                           q_rx=np.ascontiguousarray(fr.q_rx[sl]), vel=np.ascontiguousarray(fr.vel[sl])))
+    with rc.Plan(_plan_cfg(rc, fr, S, K, sensors=1)) as plan:
+        got = _Runner(rc, torch, plan, fr).run(blocks, per_batch=1)
+    k, ob = _oracle_blocks(fr, blocks)
+    rng = np.random.default_rng(79)
+    worst_rel = 0.0
+    for b in (1, 3, 4):
+        G_all = got[b][0]
+        idx = np.unique(np.concatenate([rng.integers(0, fr.n_rows * fr.n_cols, 400),
+                                        np.argsort(-np.abs(G_all))[:50]]))
+        frs = dataclasses.replace(fr, pix=np.ascontiguousarray(fr.pix[idx]))
+        P = O.bp_sliding(frs.pix.astype(np.float64), ob, b, K, k["a1"], k["a2"], k["kd"])
+        err = np.abs(G_all[idx].astype(np.complex128) - P)
+        pmax = np.abs(P).max()
+        bound = _bound(frs, k, ob, b, K, PLAIN, pmax)
+        ratio = float((err / bound).max())
+        worst_rel = max(worst_rel, float(err.max() / pmax))
+        assert ratio <= 1.0, f"aperture {b}: per-pixel bound exceeded by {ratio:.3f}"
+    _report("sliding_full_size_sampled", max_rel=worst_rel, apertures=3)
+    assert worst_rel <= PLAIN_TOL
+
+
 @pytest.mark.parametrize("n_tx,n_rx,height", [(2, 2, 0.0), (1, 3, 0.8), (1, 1, 0.0), (4, 2, 0.5)],
                          ids=["tdm2x2", "rx3-height", "rx1", "tdm4x2-height"])
 def test_sliding_channel_layouts(rc, torch, n_tx, n_rx, height):
