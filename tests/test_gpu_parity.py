@@ -361,6 +361,23 @@ def test_paper_configuration_sampled_pixels(rc, torch, precision):
     _check_image("image_paper_sampled", fr, out["image"], ora, precision, pix_index=idx)
 
 
+@pytest.mark.slow
+def test_alg1_reference_frame_sampled_pixels(rc, torch):
+    """The reference of the paper's Tab. II ablation at full size: Alg. 1 (per
+    chirp Doppler) on 1024 samples x 1024 chirps x 16 RX and the 1201 x 1201
+    Cartesian grid, as the benchmark runs it; oracle on sampled pixels and the
+    image's strongest ones."""
+    fr = synth.make_frame(synth.CONFIGS["paper-ref"], device="cuda")
+    with rc.Plan(SC.plan_config(rc, [fr], doppler=rc.RC_DOPPLER_EXACT)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch)
+    s = O.range_compress(fr.raw, O.window("hann", fr.cfg.n_samples), fr.n_fft, fr.n_bins)
+    rng = np.random.default_rng(80)
+    idx = np.unique(np.concatenate([rng.integers(0, fr.n_rows * fr.n_cols, 400),
+                                    np.argsort(-np.abs(out["image"]))[:50]]))
+    ora = SC.run_oracle(fr, spectrum=s, pix_index=idx, cfar=None, doppler="exact")
+    _check_image("alg1_reference_sampled", fr, out["image"], ora, PLAIN, pix_index=idx)
+
+
 # ---------------------------------------------------------------------------
 # ABI behaviour on the device
 # ---------------------------------------------------------------------------
