@@ -10,9 +10,9 @@
 // the interpolation table by range compression.
 //
 // gfx950 mapping.  The loop is bound by VALU issue (three quarter-rate
-// transcendentals per term: sqrt, sin, cos; three half-rate conversions and
-// shifts; eleven full-rate adds and FMAs), so the design minimises
-// instructions per term:
+// transcendentals per term: sqrt, sin, cos; two half-rate instructions, the
+// index conversion and its fraction; eleven full-rate adds and FMAs), so the
+// design minimises instructions per term:
 //  * geometry is in aperture-local wavelength units, so a path length is its
 //    carrier phase in turns and goes straight into the hardware sin/cos
 //    (which take turns);
@@ -21,7 +21,9 @@
 //  * channels sharing a TX position evaluate d_tx once per group;
 //  * the table holds (s[k], s[k+1] - s[k]) so one 16-byte buffer load and two
 //    FMAs interpolate a term; loads go through a per-row buffer descriptor, so
-//    an index outside the row reads zeros instead of faulting;
+//    an index outside the row reads zeros instead of faulting, and where the
+//    index is proven in range the load takes the bin index itself (the
+//    descriptor's 16-byte stride scales it: no shift per term);
 //  * a wave first bounds the index range of all its terms from the bounding
 //    boxes of the antenna positions; if every term is provably inside
 //    [0, n_bins - 1] it runs the loop without the per-term range test;
