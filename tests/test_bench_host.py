@@ -7,6 +7,7 @@ import shutil
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -68,3 +69,20 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_region_snr_of_a_point_on_a_flat_floor():
+    """One target of power 1e4 on a floor of unit power: 40 dB; a second target
+    inside the first one's ring is left out of that ring's mean."""
+    xs = np.arange(-1.0, 1.0, 0.025)
+    X, Y = np.meshgrid(xs, xs)
+    pix = np.stack([X.ravel(), Y.ravel()], 1)
+    img = np.ones(len(pix), np.complex128)
+    k = np.argmin(np.hypot(pix[:, 0], pix[:, 1]))
+    img[k] = 100.0
+    assert bench._region_snr_db(img, pix, np.array([[0.0, 0.0]])) == pytest.approx(40.0, abs=1e-9)
+    j = np.argmin(np.hypot(pix[:, 0] - 0.45, pix[:, 1]))
+    img2 = img.copy()
+    img2[j] = 100.0
+    snr = bench._region_snr_db(img2, pix, np.array([[0.0, 0.0], [pix[j, 0], pix[j, 1]]]))
+    assert snr == pytest.approx(40.0, abs=1e-9)
