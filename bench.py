@@ -446,12 +446,14 @@ def continuous_sar(rc, synth, torch, main_fps, drive, sub_cycles=128, K=4, depth
     }
 
 
-def _region_snr_db(img, pix, targets, rad=0.06, r_in=0.3, r_out=0.6):
+def _region_snr_db(img, pix, targets, rad=0.06, r_in=1.0, r_out=2.0):
     """Synthetic region SNR (the paper measures SNR over regions of its real
     scenes): mean over point targets of 10 log10(peak |P|^2 within rad of the
     target / mean |P|^2 over the ring r_in..r_out around it), the ring without
-    the pixels within r_out of any other target.  The scene's clutter patches
-    are not excluded."""
+    the pixels within r_out of any other target.  The ring lies beyond the
+    point response's main lobe and near side lobes, so its mean is mostly the
+    image of the receiver noise (and of the scene's clutter patches, which
+    are not excluded)."""
     t = np.asarray(targets, dtype=np.float64)[:, :2]
     p2 = np.abs(np.asarray(img)).astype(np.float64) ** 2
     out = []

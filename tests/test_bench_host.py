@@ -80,9 +80,10 @@ def test_region_snr_of_a_point_on_a_flat_floor():
     img = np.ones(len(pix), np.complex128)
     k = np.argmin(np.hypot(pix[:, 0], pix[:, 1]))
     img[k] = 100.0
-    assert bench._region_snr_db(img, pix, np.array([[0.0, 0.0]])) == pytest.approx(40.0, abs=1e-9)
+    kw = dict(r_in=0.3, r_out=0.6)
+    assert bench._region_snr_db(img, pix, np.array([[0.0, 0.0]]), **kw) == pytest.approx(40.0, abs=1e-9)
     j = np.argmin(np.hypot(pix[:, 0] - 0.45, pix[:, 1]))
     img2 = img.copy()
     img2[j] = 100.0
-    snr = bench._region_snr_db(img2, pix, np.array([[0.0, 0.0], [pix[j, 0], pix[j, 1]]]))
+    snr = bench._region_snr_db(img2, pix, np.array([[0.0, 0.0], [pix[j, 0], pix[j, 1]]]), **kw)
     assert snr == pytest.approx(40.0, abs=1e-9)
