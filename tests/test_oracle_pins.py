@@ -314,6 +314,106 @@ def test_bp_pointwise_and_permutation():
     np.testing.assert_array_equal(sub, P[10:13])
 
 
+def _indices_by_loops(pix, q_tx, q_rx, fd, a1, height=0.0):
+    """f_ind(p, m, ch) = a1 (|p - q_tx| + |p - q_rx|) + f_doppler(p) written out
+    term by term with math.sqrt, independent of the oracle's array code."""
+    P, (M, CH) = len(pix), q_tx.shape[:2]
+    f = np.zeros((P, M, CH))
+    for p in range(P):
+        for m in range(M):
+            for c in range(CH):
+                dt = math.sqrt((pix[p][0] - q_tx[m, c, 0]) ** 2 + (pix[p][1] - q_tx[m, c, 1]) ** 2 + height ** 2)
+                dr = math.sqrt((pix[p][0] - q_rx[m, c, 0]) ** 2 + (pix[p][1] - q_rx[m, c, 1]) ** 2 + height ** 2)
+                f[p, m, c] = a1 * (dt + dr) + fd[p]
+    return f
+
+
+def test_bp_abs_row_constant_spectrum():
+    """S(p) = sum_m sum_ch |w_sar[m] s(f_ind)|, the scale of every per-pixel
+    error bound.  A spectrum constant along each (m, ch) row, s = a e^{i theta},
+    interpolates to that row's value at any in-range index, so S(p) is the sum
+    of |w_sar[m]| a(m, ch) over the terms whose index lies in [0, n_bins - 1]
+    (Alg. 2's rule: other terms add nothing).  Negative window weights check
+    the magnitude of w_sar; a pixel whose every index is out of range gets 0."""
+    q_tx, q_rx, _ = _geometry(M=6, CH=3, seed=2)
+    M, CH, _ = q_tx.shape
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    rng = np.random.default_rng(21)
+    pix = np.stack([rng.uniform(-3, 3, 14), rng.uniform(1.5, 9, 14)], -1)
+    pix[-1] = [0.0, 40.0]                                # far beyond the kept bins
+    fd = rng.uniform(-2, 2, 14)
+    amp = rng.uniform(0.5, 2.0, (M, CH))
+    theta = rng.uniform(-np.pi, np.pi, (M, CH))
+    w = rng.uniform(-1.0, 1.0, M)
+    f = _indices_by_loops(pix, q_tx, q_rx, fd, k["a1"])
+    for nb in (int(f[:-1].max()) + 3, int(np.median(f[:-1])) + 1):   # all in range / about half out
+        s = np.broadcast_to((amp * np.exp(1j * theta))[:, :, None], (M, CH, nb)).copy()
+        S = O.bp_alg2_abs(pix, q_tx, q_rx, fd, s, w, k["a1"])
+        inside = (f >= 0) & (f <= nb - 1)
+        expect = np.sum(np.abs(w)[None, :, None] * amp[None] * inside, axis=(1, 2))
+        np.testing.assert_allclose(S, expect, rtol=1e-13, atol=0)
+        assert S[-1] == 0.0
+    assert 0 < inside[:-1].mean() < 1                    # the second case drops part of the terms
+    # every term in range: N_ch sum |w| for unit rows
+    s1 = np.broadcast_to(np.exp(1j * theta)[:, :, None], (M, CH, int(f[:-1].max()) + 3)).copy()
+    S1 = O.bp_alg2_abs(pix[:-1], q_tx, q_rx, fd[:-1], s1, w, k["a1"])
+    np.testing.assert_allclose(S1, CH * np.abs(w).sum(), rtol=1e-13)
+
+
+@pytest.mark.parametrize("height", [0.0, 0.7])
+def test_bp_abs_linear_ramp_closed_form(height):
+    """A row e^{i theta} (1 + beta k) with real beta > 0 interpolates to
+    e^{i theta} (1 + beta f) exactly, so S(p) = sum |w_sar[m]| (1 + beta
+    f_ind(p, m, ch)) with the indices from the distances written out term by
+    term: pins the index (a1, the Doppler table, the 3-D distances) inside S."""
+    q_tx, q_rx, _ = _geometry(M=7, CH=2, seed=3)
+    M, CH, _ = q_tx.shape
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    rng = np.random.default_rng(22)
+    pix = np.stack([rng.uniform(-3, 3, 12), rng.uniform(2, 8, 12)], -1)
+    fd = rng.uniform(-1.5, 1.5, 12)
+    beta = 0.037
+    f = _indices_by_loops(pix, q_tx, q_rx, fd, k["a1"], height)
+    nb = int(f.max()) + 4
+    theta = rng.uniform(-np.pi, np.pi, (M, CH))
+    s = np.exp(1j * theta)[:, :, None] * (1 + beta * np.arange(nb))[None, None, :]
+    w = rng.uniform(-1.0, 1.0, M)
+    S = O.bp_alg2_abs(pix, q_tx, q_rx, fd, s, w, k["a1"], height=height)
+    expect = np.sum(np.abs(w)[None, :, None] * (1 + beta * f), axis=(1, 2))
+    np.testing.assert_allclose(S, expect, rtol=1e-12)
+
+
+def test_bp_abs_bounds_the_image_and_is_reached_when_coherent():
+    """|P(p)| <= S(p) (triangle inequality) on random spectra and windows, and
+    equality where every term has the same phase: the matched spectrum of the
+    coherent-gain pin focuses p0 to S(p0) = N_ch sum(w)."""
+    q_tx, q_rx, _ = _geometry(M=16, CH=3)
+    M, CH, _ = q_tx.shape
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], 2.5e6, 512)
+    rng = np.random.default_rng(23)
+    pix = np.stack([rng.uniform(-3, 3, 60), rng.uniform(1, 9, 60)], -1)
+    fd = rng.uniform(-1, 1, 60)
+    for _ in range(3):
+        s = synth.random_spectrum(rng, (M, CH, 130)).astype(np.complex128)
+        w = rng.uniform(-1, 1, M)
+        P = O.bp_alg2(pix, q_tx, q_rx, fd, s, w, k["a1"], k["a2"])
+        S = O.bp_alg2_abs(pix, q_tx, q_rx, fd, s, w, k["a1"])
+        assert np.all(np.abs(P) <= S * (1 + 1e-12))
+        assert np.all(S > 0)
+    p0 = 11
+    dh0 = _dist(pix[p0], q_tx) + _dist(pix[p0], q_rx)
+    f0 = k["a1"] * dh0 + fd[p0]
+    kk = np.arange(160.0)
+    s = np.exp(2j * np.pi * dh0 / k["lam"])[:, :, None] * (1 + 0.01 * (kk[None, None, :] - f0[:, :, None]))
+    w = O.window("hann", M) + 0.1
+    P = O.bp_alg2(pix, q_tx, q_rx, fd, s, w, k["a1"], k["a2"])
+    S = O.bp_alg2_abs(pix, q_tx, q_rx, fd, s, w, k["a1"])
+    assert S[p0] == pytest.approx(CH * w.sum(), rel=1e-12)
+    assert abs(P[p0]) == pytest.approx(S[p0], rel=1e-9)
+    others = np.arange(60) != p0
+    assert np.all(np.abs(P[others]) < S[others])
+
+
 def _point_target_frame(n_rx=8, speed=2.0, seed=11):
     cfg = synth.SceneConfig("pt", n_samples=128, n_chirps=64, n_tx=1, n_rx=n_rx,
                             box=(-2.0, 2.0, 3.0, 7.0), nx=41, ny=41, speed=speed,
