@@ -216,6 +216,19 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out);
 /* Bytes of device memory one frame slot of this descriptor needs. */
 rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes);
 
+/* Checks one frame (host) against a plan descriptor (host) exactly as
+ * rc_process_batch() checks it before enqueuing anything, without a plan or a
+ * GPU (no device pointer is dereferenced; q_tx, q_rx, vel and w_sar are
+ * read).  RC_OK or RC_EINVAL with the reason in rc_last_error().  Besides the
+ * limits and sizes this includes the phase range of the single-precision
+ * forms (Alg. 2's exp(a2 d_hyp) takes the whole two-way path in wavelengths):
+ * with RC_PREC_FP32, paths that can contribute - those whose index
+ * a1 d_hyp + f_doppler can lie in [0, n_bins - 1] - must stay within 2^16
+ * wavelengths, taking |f_doppler| <= 2 kd max|v| for the plan's own Doppler
+ * table and for Alg. 1, and |f_doppler| <= n_bins - 1 for a caller's table
+ * (which callers must respect); longer frames need RC_PREC_FP32_SPLIT. */
+rc_status rc_frame_validate(const rc_plan_desc* desc, const rc_frame* frame);
+
 /* Enqueue n_frames frames on stream (Alg. 2 pipeline, steps 1-4 above).
  * Each frame takes a free slot.  Sub-apertures of one stream are processed
  * in the order given (within the batch and across calls, on any streams:

@@ -69,7 +69,7 @@ __device__ u32x4 struct_buffer_load_b128(__amdgpu_buffer_rsrc_t rsrc, int vindex
 // Per-form geometry of one term.  Plain (Alg. 2): d = sqrt(|P|^2 + |q|^2 -
 // 2 P.q) from the per-row uniforms (-2 q, |q|^2) and the pixel's |P|^2 split
 // into a float and a correction.  Split-phase: d = R + delta with
-// delta = N / (d + R), N = |P - q|^2 - R^2 = |q|^2 - 2 P.q (two FMAs),
+// N = |P - q|^2 - R^2 = |q|^2 - 2 P.q (two FMAs) and delta = N / (d + R),
 // d = sqrt(R^2 + N); only delta (|delta| <= |q|) and the reference phase
 // frac(2R) enter the phase, so its rounding error scales with the aperture
 // size, not with the range.  Exact (Alg. 1): each leg also contributes its own
@@ -80,8 +80,28 @@ struct Leg {
   float dop;  // exact only: Doppler index shift of the leg
 };
 
-template <int FORM>
-__device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p) {
+// Per-pixel constants of the split form's series: h = 1 / (2R), k = 1 / R^2.
+struct PixAux {
+  float h, k;
+};
+
+// Split-phase offset by series.  With u = N / R^2,
+//   delta = sqrt(R^2 + N) - R = (N / (2R)) (1 + u G(u)),
+//   G(u) = -1/4 + u/8 - 5u^2/64 + 7u^3/128 - ...
+// (the binomial series of sqrt(1 + u)).  G is evaluated as the cubic that
+// interpolates it at the four Chebyshev nodes of [-kSeriesU, kSeriesU]
+// (kSeriesU = 0.1): with the coefficients rounded to float, 1 + u G(u) is off
+// by at most 5.7e-8 of itself there (the Taylor cubic: 4.5e-7).  Far from the
+// aperture (R above ~20 times the antennas' spread) delta then costs five
+// FMA-class instructions and four multiplies instead of a square root and a
+// reciprocal, both quarter-rate; waves with any pixel closer take the exact
+// form.
+constexpr float kSeriesU = 0.1f;
+constexpr float kG0 = -0.24999947845935822f, kG1 = 0.12499959766864777f, kG2 = -0.0785374641418457f,
+                kG3 = 0.05501168593764305f;
+
+template <int FORM, bool SERIES>
+__device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p, const PixAux x_) {
   Leg<FORM> l;
   if constexpr (FORM == kBpExact) {
     const float x = p.x - q.x, y = p.y - q.y;
@@ -89,7 +109,16 @@ __device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p) {
     l.dop = fmaf(x, q.z, y * q.w) * __builtin_amdgcn_rcpf(l.d);
   } else if constexpr (FORM == kBpSplit) {
     const float n = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
-    l.d = n * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, n)) + p.z);
+    if constexpr (SERIES) {
+      const float u = n * x_.k;
+      const float w = n * x_.h;
+      float g = fmaf(kG3, u, kG2);
+      g = fmaf(g, u, kG1);
+      g = fmaf(g, u, kG0);
+      l.d = fmaf(w * u, g, w);
+    } else {
+      l.d = n * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, n)) + p.z);
+    }
     l.dop = 0.f;
   } else {
     l.d = __builtin_amdgcn_sqrtf(fmaf(q.x, p.x, fmaf(q.y, p.y, p.z)) + q.z);
@@ -111,7 +140,7 @@ struct Stage {
 // multiply-accumulates of the current U rows, so their latency overlaps the
 // transcendentals.  U = min(CHG, 4) rows per stage; the TX leg is evaluated
 // once per group of CHG rows.
-template <int CHG, int FORM, bool CHECKED, int SUMS>
+template <int CHG, int FORM, bool CHECKED, int SUMS, bool SERIES = false>
 __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int row_end, const float4 p,
                                          const float fidx, float (&out_re)[SUMS], float (&out_im)[SUMS]) {
   constexpr bool EXACT = FORM == kBpExact;
@@ -126,8 +155,17 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   const float2* wp = SUMS == 3 ? a.roww + row_begin / a.n_ch : nullptr;
   const float2* wend = SUMS == 3 ? a.roww + row_end / a.n_ch : nullptr;
   const int n = row_end - row_begin;  // a multiple of CHG
-  // per-pixel index base: plain f_doppler; split the index of the reference path
-  const float fb = fidx;
+  // per-pixel index base: plain f_doppler; split the index of the reference
+  // path, less a1 frac(2R): the split form's TX leg carries the reference
+  // phase frac(2R), so a term's phase and index both come from one sum
+  const float fb = FORM == kBpSplit ? fmaf(-a.a1, p.w, fidx) : fidx;
+  // split form's series: 1 / (2R) and 1 / R^2 (p.z = R)
+  PixAux aux{0.f, 0.f};
+  if constexpr (FORM == kBpSplit && SERIES) {
+    const float ir = __builtin_amdgcn_rcpf(p.z);
+    aux.h = 0.5f * ir;
+    aux.k = ir * ir;
+  }
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
   // SUMS == 3: the plain, cos- and sin-weighted sums over the chirps done,
   // in this lane's LDS slot my[0] = (re: plain, cos, sin), my[1] = (im: ...)
@@ -142,9 +180,8 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   Leg<FORM> tx;
 
   auto tx_leg = [&](int r) {
-    tx = leg<FORM>(gq[r / CHG], p);
-    if constexpr (FORM == kBpPlain) tx.d += p.w;
-    if constexpr (FORM == kBpExact) tx.d += p.w;
+    tx = leg<FORM, SERIES>(gq[r / CHG], p, aux);
+    tx.d += p.w;  // plain, exact: the pixel's rounding correction; split: frac(2R)
   };
   auto issue = [&](int r, Stage<U>& st) {
     // the stage's row uniforms as one vector, so they arrive in one scalar load
@@ -155,12 +192,11 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
     for (int j = 0; j < U; ++j) q[j] = make_float4(u[4 * j], u[4 * j + 1], u[4 * j + 2], u[4 * j + 3]);
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const Leg<FORM> rx = leg<FORM>(q[j], p);
+      const Leg<FORM> rx = leg<FORM, SERIES>(q[j], p, aux);
       float f, turn;
       if constexpr (FORM == kBpSplit) {
-        const float dlt = tx.d + rx.d;
-        f = fmaf(a.a1, dlt, fb);
-        turn = p.w + dlt;
+        turn = tx.d + rx.d;  // frac(2R) + delta_tx + delta_rx
+        f = fmaf(a.a1, turn, fb);
       } else if constexpr (FORM == kBpExact) {
         const float d_hyp = tx.d + rx.d;
         f = fmaf(a.a1, d_hyp, tx.dop + rx.dop);
@@ -188,9 +224,11 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       } else {
         // 0 <= i <= n_bins - 1 by the wave's range proof: the record index
         // goes to the load, which scales it by the 16-byte stride (no shift
-        // per term)
+        // per term).  With a non-zero stride the range check counts records,
+        // so the descriptor's bound is n_bins: an index past the row would
+        // read zeros, never the next row.
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(tab + (size_t)(r + j) * a.n_bins), (short)16, row_bytes, kRsrcWord3);
+            (void*)(tab + (size_t)(r + j) * a.n_bins), (short)16, a.n_bins, kRsrcWord3);
         st.e[j] = struct_buffer_load_b128(rs, i, 0, 0, 0);
       }
     }
@@ -349,10 +387,29 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
 
   float re[SUMS], im[SUMS];
   const float fb = SPLIT ? fi_p : fdp;
-  if (__all(inside))
-    bp_terms<CHG, FORM, false, SUMS>(a, row_begin, row_end, p, fb, re, im);
-  else
-    bp_terms<CHG, FORM, true, SUMS>(a, row_begin, row_end, p, fb, re, im);
+  if constexpr (SPLIT) {
+    // the series of the split-phase offset holds where |N| / R^2 <= kSeriesU
+    // for every antenna: |N| <= 2 R Q + Q^2, Q the antennas' largest distance
+    // from the aperture centre
+    const float qr = a.q_max / p.z;
+    const bool series = p.z > 0.f && fmaf(qr, qr, 2.f * qr) <= kSeriesU;
+    if (__all(series)) {
+      if (__all(inside))
+        bp_terms<CHG, FORM, false, SUMS, true>(a, row_begin, row_end, p, fb, re, im);
+      else
+        bp_terms<CHG, FORM, true, SUMS, true>(a, row_begin, row_end, p, fb, re, im);
+    } else {
+      if (__all(inside))
+        bp_terms<CHG, FORM, false, SUMS>(a, row_begin, row_end, p, fb, re, im);
+      else
+        bp_terms<CHG, FORM, true, SUMS>(a, row_begin, row_end, p, fb, re, im);
+    }
+  } else {
+    if (__all(inside))
+      bp_terms<CHG, FORM, false, SUMS>(a, row_begin, row_end, p, fb, re, im);
+    else
+      bp_terms<CHG, FORM, true, SUMS>(a, row_begin, row_end, p, fb, re, im);
+  }
   if (live) {
     const int64_t n_pix = (int64_t)a.n_rows * a.n_cols;
 #pragma unroll

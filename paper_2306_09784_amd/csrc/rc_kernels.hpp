@@ -147,6 +147,7 @@ struct BpFrame {
   float f_margin;
   float f_slack;          // largest |Doppler index| a term can carry (exact form)
   float h2;               // (antenna height / wavelength)^2 (0: planar geometry)
+  float q_max;            // largest antenna distance from the aperture centre (wavelengths)
 };
 
 constexpr int kBpMaxFrames = 16;  // frames per launch (descriptors travel as kernel arguments)

@@ -41,6 +41,10 @@ rc_status fail(rc_status st, const char* fmt, ...) {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kDetPrefix = 1024;  // detections copied back asynchronously per frame
+// longest two-way path, in wavelengths, whose phase the single-precision forms
+// hand to the hardware sine and cosine (their argument reduction is verified
+// to 2^16 turns)
+constexpr double kMaxPathTurns = 65536.0;
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int64_t v) {
@@ -373,6 +377,30 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
   } else {
     return fail(RC_EINVAL, "frame %lld: unknown input_kind %d", (long long)f.frame_id, (int)f.input_kind);
   }
+  // The single-precision forms feed a term's whole two-way path, in
+  // wavelengths, to the hardware sine and cosine (Alg. 2's exp(a2 d_hyp)).
+  // Their argument reduction is verified up to kMaxPathTurns turns, and the
+  // path's float rounding stays below 1e-3 turns there.  A term contributes
+  // only while its index a1 d_hyp + f_doppler lies in [0, n_bins - 1], so
+  // every contributing path is at most (n_bins - 1 + F) / a1 long, F bounding
+  // -f_doppler: twice kd |v| for the plan's own table and for Alg. 1, and
+  // n_bins - 1 for a caller's table (the documented bound on its values).
+  // Longer paths need the split-phase form, whose phase never holds the
+  // whole path.
+  if (d.precision != RC_PREC_FP32_SPLIT) {
+    const double c = d.radar.c > 0 ? d.radar.c : 299792458.0;
+    const double df = f.fs / f.n_fft;
+    const double a1 = d.radar.bandwidth / d.radar.t_chirp / (c * df);  // bins per metre of path
+    double vmax = 0;
+    for (int m = 0; m < f.n_chirps; ++m) vmax = std::max(vmax, std::hypot((double)f.vel[2 * m], (double)f.vel[2 * m + 1]));
+    const double F = f.f_doppler ? (double)(f.n_bins - 1) : 2.0 * d.radar.f0 / (c * df) * vmax;
+    const double turns = (f.n_bins - 1 + F) / a1 * d.radar.f0 / c;
+    if (!(turns <= kMaxPathTurns))
+      return fail(RC_EINVAL,
+                  "frame %lld: paths up to %.0f wavelengths can contribute, beyond the %.0f the single-precision "
+                  "phase supports; use RC_PREC_FP32_SPLIT",
+                  (long long)f.frame_id, turns, kMaxPathTurns);
+  }
   return RC_OK;
 }
 
@@ -447,6 +475,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   };
   const bool exact = d.doppler == RC_DOPPLER_EXACT;
   double vmax = 0;
+  double q_max = 0;  // largest antenna distance from the aperture centre, wavelengths
   for (int64_t r = 0; r < rows; ++r) {
     float x, y;
     // exact form: positions and kd v(m) (bins per unit radial speed)
@@ -456,7 +485,9 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
     rowq[r] = exact ? make_float4(x, y, kvx, kvy)
                     : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
     rlx = std::min(rlx, x); rly = std::min(rly, y); rhx = std::max(rhx, x); rhy = std::max(rhy, y);
+    q_max = std::max(q_max, std::hypot((double)x, (double)y));
     local(f.q_tx + 2 * r, x, y);
+    q_max = std::max(q_max, std::hypot((double)x, (double)y));
     if (r % chg == 0)
       grpq[r / chg] = exact ? make_float4(x, y, kvx, kvy)
                             : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
@@ -609,6 +640,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   // ulps of n_bins; the margin keeps such waves on the range-tested path
   ba.f_margin = (float)(1e-3 + 64.0 * f.n_bins * std::ldexp(1.0, -24));
   ba.h2 = (float)(f.height * inv_lam * f.height * inv_lam);
+  ba.q_max = (float)(q_max * (1.0 + 1e-6));
   if (n_kb > 1 && (int64_t)n_kb * planes * n_pix > s.partial_cap)
     return fail(RC_EINVAL, "frame %lld: %d chirp blocks of %lld pixels exceed the slot's partial buffer",
                 (long long)f.frame_id, n_kb, (long long)n_pix);
@@ -724,6 +756,17 @@ rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes) {
   if (!bytes) return fail(RC_EINVAL, "bytes is NULL");
   *bytes = (int64_t)slot_sizes(*desc).total();
   return RC_OK;
+}
+
+rc_status rc_frame_validate(const rc_plan_desc* desc, const rc_frame* frame) {
+  g_err.clear();
+  rc_status st = validate_desc(desc);
+  if (st != RC_OK) return st;
+  if (!frame) return fail(RC_EINVAL, "frame is NULL");
+  Plan shape;  // the descriptor's limits only: nothing is allocated
+  shape.d = *desc;
+  shape.planes = desc->sliding_sensors > 0 ? sliding_planes(*desc) : 0;
+  return validate_frame(&shape, *frame);
 }
 
 rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {

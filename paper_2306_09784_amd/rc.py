@@ -111,7 +111,7 @@ DETECTION_DTYPE = np.dtype([("pixel", "<i4"), ("power", "<f4"), ("threshold", "<
 
 #: every entry point declared in include/rc.h
 ENTRY_POINTS = [
-    "rc_plan_create", "rc_plan_slot_bytes", "rc_process_batch", "rc_poll", "rc_detections",
+    "rc_plan_create", "rc_plan_slot_bytes", "rc_frame_validate", "rc_process_batch", "rc_poll", "rc_detections",
     "rc_image", "rc_stage_times", "rc_frame_release", "rc_plan_destroy", "rc_last_error", "rc_grid_cartesian",
     "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar",
 ]
@@ -137,6 +137,7 @@ def _load():
     sig = {
         "rc_plan_create": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(C.c_void_p)]),
         "rc_plan_slot_bytes": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(C.c_int64)]),
+        "rc_frame_validate": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(rc_frame)]),
         "rc_process_batch": (C.c_int, [vp, C.POINTER(rc_frame), i32, vp]),
         "rc_poll": (C.c_int, [vp, i64]),
         "rc_detections": (C.c_int, [vp, i64, C.POINTER(rc_detection), i64, C.POINTER(C.c_int64)]),
@@ -254,6 +255,13 @@ def slot_bytes(cfg: PlanConfig) -> int:
     d = cfg.desc()
     check(lib.rc_plan_slot_bytes(C.byref(d), C.byref(out)), "rc_plan_slot_bytes")
     return out.value
+
+
+def validate_frame(cfg: PlanConfig, frame) -> int:
+    """rc_frame_validate: the status rc_process_batch would give the frame
+    under a plan of this configuration (host only, no GPU)."""
+    d = cfg.desc()
+    return lib.rc_frame_validate(C.byref(d), C.byref(frame))
 
 
 def _ptr(t) -> Optional[int]:

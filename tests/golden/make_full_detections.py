@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Writes the oracle's CA-CFAR detection lists of the two full-size frames.
 
-    python tests/golden/make_full_detections.py [--procs N] [--only NAME]
+    python tests/golden/make_full_detections.py [--procs N] [--only NAME] [--fingerprint-only]
 
 For the benchmark's frame (plain-large: 1024 IQ samples x 512 TDM cycles x 16
 channels on the 1201 x 1201 Cartesian grid) and the paper's configuration
@@ -14,7 +14,9 @@ DFT, Doppler table of Sec. III-D, Alg. 2 over every pixel), runs its CA-CFAR
   * every tested cell whose power lies within 5 % of its threshold (the cells
     whose decision a reduced-precision image may legitimately flip), and
   * SHA-256 digests of the synthetic beat cube and pixel list the values were
-    formed from, so a test can confirm it feeds the GPU the same frame.
+    formed from, and a seeded sample of their values, so a test can confirm it
+    feeds the GPU the same frame (to the last-bit rounding another host's or
+    the GPU's synthesis may differ by).
 
 Only the oracle and the seeded input generator are used; nothing here touches
 the HIP library.  Alg. 2 runs on disjoint pixel slices in a pool of
@@ -59,6 +61,27 @@ def _bp_slice(bounds):
 
 def digest(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+SAMPLE_SEED, SAMPLE_N = 4242, 2048
+
+
+def sample_index(n: int) -> np.ndarray:
+    """Seeded positions of the elements a fingerprint records."""
+    return np.sort(np.random.default_rng(SAMPLE_SEED).choice(n, size=min(n, SAMPLE_N), replace=False))
+
+
+def fingerprint(fr) -> dict:
+    """A seeded sample of the beat cube and of the pixel list.  Another host's
+    libm (or the GPU) may round the synthesis differently in the last bit, so
+    a test recognises the frame by these values to a tolerance, not by its
+    digest alone."""
+    raw = np.ascontiguousarray(fr.raw).reshape(-1)
+    pix = np.ascontiguousarray(fr.pix).reshape(-1)
+    ri, pi = sample_index(raw.size), sample_index(pix.size)
+    return {"sample_seed": SAMPLE_SEED,
+            "raw_sample": [[float(v.real), float(v.imag)] for v in raw[ri]],
+            "pix_sample": [float(v) for v in pix[pi]]}
 
 
 def frame_of(name: str):
@@ -155,6 +178,7 @@ def make(name: str, procs: int) -> dict:
         "n_rows": fr.n_rows, "n_cols": fr.n_cols, "n_bins": fr.n_bins,
         "guard": GUARD, "train": TRAIN, "pfa": PFA, "near_rel": NEAR,
         "raw_sha256": digest(fr.raw), "pix_sha256": digest(fr.pix),
+        **fingerprint(fr),
         "max_power": float(power.max()),
         "detections": [[int(i), float(a), float(b)] for i, a, b in zip(idx, pw, thr)],
         "near": [[int(near_idx[j]), float(p[tuple(near[j])]), float(t[tuple(near[j])])] for j in order],
@@ -168,11 +192,22 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--procs", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--only", default=None)
+    ap.add_argument("--fingerprint-only", action="store_true",
+                    help="re-synthesise the frames and refresh only their digests and samples, after checking "
+                         "that the frames are the ones the stored lists were formed from")
     a = ap.parse_args()
     for name in ("plain-large", "paper-polar"):
         if a.only and name != a.only:
             continue
-        rec = make(name, a.procs)
+        if a.fingerprint_only:
+            with open(OUT.format(name)) as f:
+                rec = json.load(f)
+            fr = frame_of(name)
+            if digest(fr.raw) != rec["raw_sha256"] or digest(fr.pix) != rec["pix_sha256"]:
+                raise SystemExit(f"{name}: this host synthesises another frame; recompute the lists instead")
+            rec.update(fingerprint(fr))
+        else:
+            rec = make(name, a.procs)
         with open(OUT.format(name), "w") as f:
             json.dump(rec, f, separators=(",", ":"))
             f.write("\n")

@@ -180,3 +180,71 @@ def test_polar_pixel_count_reported():
     q = O.polar_grid_params((-15, 15, 1, 31), (0.0, 0.0), synth.RADAR["bandwidth"], lam, L)
     n = q["nr"] * q["nth"]
     assert 100_000 < n < 400_000
+
+
+def _long_frame(rc, n_bins, n_samples=2048, f_doppler=None):
+    """A frame of 2048 samples (fs = N / T_P, DFT 4096) keeping n_bins bins,
+    4 chirps x 2 RX at 2 m/s; data and pixels are placeholders the check does
+    not read."""
+    M, CH = 4, 2
+    q = np.zeros((M, CH, 2), np.float32)
+    q[..., 0] = np.arange(CH) * 0.002
+    vel = np.tile(np.array([[2.0, 0.0]], np.float32), (M, 1))
+    fs = n_samples / synth.RADAR["t_chirp"]
+    dummy = np.zeros(16, np.float32)
+    return rc.Plan.make_frame(1, data=dummy, q_tx=q, q_rx=q.copy(), vel=vel, pixels=dummy, n_rows=4, n_cols=4,
+                              n_bins=n_bins, n_fft=2 * n_samples, fs=fs, n_samples=n_samples,
+                              f_doppler=f_doppler), (q, vel)
+
+
+def test_single_precision_phase_range_guard(rc):
+    """Alg. 2's exp(a2 d_hyp): the single-precision forms hand the whole path in
+    wavelengths to the hardware sine/cosine, verified to 2^16 turns.  A frame
+    whose bins reach paths beyond that is refused for RC_PREC_FP32 and the
+    exact form, and accepted by the split-phase form."""
+    R = synth.RADAR
+    lam = R["c"] / R["f0"]
+    df = 2048 / R["t_chirp"] / 4096
+    a1 = R["bandwidth"] / R["t_chirp"] / (R["c"] * df)        # bins per metre of path
+    limit_bins = int(65536 * lam * a1)                           # ~1630 bins here
+    base = dict(n_samples_max=2048, n_fft_max=4096, n_bins_max=4096, n_chirps_max=4, n_channels_max=2,
+                n_pix_max=16)
+    ok_bins, bad_bins = limit_bins - 8, limit_bins + 8
+    for prec, dop in ((rc.RC_PREC_FP32, rc.RC_DOPPLER_AVERAGE), (rc.RC_PREC_FP32, rc.RC_DOPPLER_EXACT)):
+        cfg = _cfg(rc, **base, precision=prec, doppler=dop)
+        fr, keep = _long_frame(rc, ok_bins)
+        assert rc.validate_frame(cfg, fr) == rc.RC_OK, rc.last_error()
+        fr, keep = _long_frame(rc, bad_bins)
+        assert rc.validate_frame(cfg, fr) == rc.RC_EINVAL
+        assert "RC_PREC_FP32_SPLIT" in rc.last_error()
+    split = _cfg(rc, **base, precision=rc.RC_PREC_FP32_SPLIT)
+    fr, keep = _long_frame(rc, 4096)
+    assert rc.validate_frame(split, fr) == rc.RC_OK, rc.last_error()
+    # a caller's Doppler table may hold up to n_bins - 1 bins: the bound doubles
+    plain = _cfg(rc, **base)
+    table = np.zeros(16, np.float32)
+    half = limit_bins // 2 - 8
+    fr, keep = _long_frame(rc, half)
+    assert rc.validate_frame(plain, fr) == rc.RC_OK
+    fr, keep = _long_frame(rc, ok_bins, f_doppler=table)
+    assert rc.validate_frame(plain, fr) == rc.RC_EINVAL
+    fr, keep = _long_frame(rc, half, f_doppler=table)
+    assert rc.validate_frame(plain, fr) == rc.RC_OK, rc.last_error()
+
+
+def test_benchmark_frames_pass_the_phase_range_guard(rc):
+    """The benchmark's and the paper's frames stay far inside 2^16 turns."""
+    for name in ("plain-large", "paper-polar", "plain-small"):
+        cfg = synth.CONFIGS[name]
+        M, CH = cfg.n_chirps, cfg.n_channels
+        q = np.zeros((M, CH, 2), np.float32)
+        vel = np.tile(np.array([[9.0, 0.0]], np.float32), (M, 1))
+        fs = synth.sample_rate(cfg)
+        n_bins = int(synth.required_bins(cfg, q, q, vel))
+        dummy = np.zeros(16, np.float32)
+        fr = rc.Plan.make_frame(1, data=dummy, q_tx=q, q_rx=q.copy(), vel=vel, pixels=dummy, n_rows=4, n_cols=4,
+                                n_bins=n_bins, n_fft=cfg.n_fft, fs=fs, n_samples=cfg.n_samples)
+        pc = _cfg(rc, n_samples_max=cfg.n_samples, n_fft_max=cfg.n_fft, n_bins_max=n_bins, n_chirps_max=M,
+                  n_channels_max=CH, n_pix_max=16)
+        assert rc.validate_frame(pc, fr) == rc.RC_OK, (name, rc.last_error())
+
