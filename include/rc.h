@@ -273,6 +273,40 @@ rc_status rc_frame_release(void* plan, int64_t frame_id);
 /* Synchronises outstanding work and frees every resource of the plan. */
 rc_status rc_plan_destroy(void* plan);
 
+/* ---------------------------------------------------------------------------
+ * One frame with no allocation.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Runs the
+ * pipeline of rc_process_batch() (range compression, tables, back-projection,
+ * CA-CFAR and ordered compaction) for one frame without a plan.  Every
+ * intermediate lives in one scratch array the library holds on each GPU from
+ * its load to the end of the process (RC_STATIC_SCRATCH_BYTES); the call makes
+ * no hipMalloc, hipFree or pinned allocation.  The geometry is copied from the
+ * host arrays with hipMemcpyAsync from pageable memory (read before the call
+ * returns).
+ *   desc        the settings of a plan (radar, windows, precision, Doppler
+ *               mode, CFAR); its limits bound the frame as in rc_process_batch;
+ *               max_rechecks and sliding_sensors must be 0;
+ *   frame       as for rc_process_batch; image_out (device) is required;
+ *               sliding must be RC_SLIDE_OFF;
+ *   detections  device rc_detection[det_cap]: the first det_cap detections in
+ *               ascending pixel order; n_det (device int64): their true count;
+ *   stream      the HIP stream (NULL = default) every step is enqueued on.
+ * Returns after enqueuing; the outputs are valid once the stream reaches the
+ * end of the call.  RC_EINVAL for a frame that needs more than
+ * RC_STATIC_SCRATCH_BYTES of scratch (interpolation table 16 B per chirp,
+ * channel and bin; about 40 B per pixel plus 8 B per pixel and chirp block of
+ * partial images), or more than 16384 chirp x channel rows, and for the
+ * arguments rc_process_batch refuses.  All calls on one GPU share its scratch:
+ * calls whose work overlaps on that GPU (other streams, other threads without
+ * a stream order) race and give wrong results; nothing in the scratch needs to
+ * start cleared, so calls in stream order are independent of each other. */
+#define RC_STATIC_SCRATCH_BYTES (32 << 20)
+rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* frame,
+                                  rc_detection* detections, int64_t det_cap, int64_t* n_det,
+                                  void* stream);
+
 /* Thread-local description of the last error ("" if none). */
 const char* rc_last_error(void);
 

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -746,9 +747,170 @@ rc_status finish_batch(Plan* p, const std::vector<Slot*>& slot, const rc_frame* 
   return RC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// One frame without a plan and without allocating: every intermediate of the
+// pipeline (interpolation table, geometry rows, pixel tables, partial images,
+// CFAR mask and per-cell records) lives in `scratch`, a file-scope device
+// array of RC_STATIC_SCRATCH_BYTES that each GPU holds from the library's load
+// to the end of the process.  Its device address comes from
+// hipGetSymbolAddress, once per device; host code uses only that address.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticMaxRows = 16384;  // chirps x channels of one static frame
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;                    // guards the two tables below
+void* g_static_scratch[kStaticMaxDevices] = {};
+// host staging of one frame's geometry rows (pageable: the copy reads it
+// before hipMemcpyAsync returns)
+float g_static_geo[8 * kStaticMaxRows + kStaticMaxRows + 4096 + 4];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[RC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+struct StaticLayout {
+  size_t pairs, geo, fd, pixc, fbase, partials, mask, det_cell, total;
+};
+
+StaticLayout static_layout(const rc_plan_desc& d, const rc_frame& f, int n_kb) {
+  StaticLayout l{};
+  const size_t rows = (size_t)f.n_chirps * f.n_channels;
+  const size_t n_pix = (size_t)f.n_rows * f.n_cols;
+  const size_t n_s = f.input_kind == RC_INPUT_RAW ? (size_t)f.n_samples : 0;
+  l.pairs = round_up(rows * f.n_bins * sizeof(float4));
+  l.geo = round_up(((8 * rows + f.n_chirps + n_s + 3) & ~size_t(3)) * sizeof(float));
+  l.fd = round_up(n_pix * sizeof(float));
+  l.pixc = round_up(n_pix * sizeof(float4));
+  l.fbase = d.precision == RC_PREC_FP32_SPLIT ? round_up(n_pix * sizeof(float)) : 0;
+  l.partials = n_kb > 1 ? round_up((size_t)n_kb * n_pix * sizeof(float2)) : 0;
+  l.mask = round_up((size_t)f.n_rows * ((f.n_cols + 63) / 64) * sizeof(unsigned long long));
+  l.det_cell = round_up(n_pix * sizeof(rc_detection));
+  l.total = l.pairs + l.geo + l.fd + l.pixc + l.fbase + l.partials + l.mask + l.det_cell;
+  return l;
+}
+
 }  // namespace
 
 extern "C" {
+
+rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* frame, rc_detection* detections,
+                                  int64_t det_cap, int64_t* n_det, void* stream) {
+  g_err.clear();
+  rc_status st = validate_desc(desc);
+  if (st != RC_OK) return st;
+  if (!frame) return fail(RC_EINVAL, "frame is NULL");
+  const rc_frame& f = *frame;
+  if (desc->max_rechecks != 0 || desc->sliding_sensors != 0 || f.sliding != RC_SLIDE_OFF)
+    return fail(RC_EINVAL, "the static entry point has no double-precision recheck and no continuous SAR");
+  if (!f.image_out) return fail(RC_EINVAL, "frame %lld: image_out is required", (long long)f.frame_id);
+  if (!n_det || det_cap < 0 || (det_cap > 0 && !detections))
+    return fail(RC_EINVAL, "detections, det_cap and n_det must describe a device buffer and a device count");
+  Plan shape;  // the descriptor only: no slot, nothing allocated
+  shape.d = *desc;
+  shape.d.stage_timing = 0;
+  st = validate_frame(&shape, f);
+  if (st != RC_OK) return st;
+  const int64_t rows = (int64_t)f.n_chirps * f.n_channels;
+  if (rows > kStaticMaxRows)
+    return fail(RC_EINVAL, "frame %lld: %lld chirp x channel rows, the static entry point takes at most %lld",
+                (long long)f.frame_id, (long long)rows, (long long)kStaticMaxRows);
+  const int n_kb = frame_chirp_blocks(&shape, f);
+  const StaticLayout L = static_layout(shape.d, f, n_kb);
+  if (L.total > (size_t)RC_STATIC_SCRATCH_BYTES)
+    return fail(RC_EINVAL, "frame %lld needs %zu bytes of scratch; the static scratch holds %lld",
+                (long long)f.frame_id, L.total, (long long)RC_STATIC_SCRATCH_BYTES);
+  int dev = 0;
+  RC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kStaticMaxDevices) return fail(RC_EINVAL, "device %d beyond the static table", dev);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_scratch[dev]) {
+    void* ptr = nullptr;
+    RC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_static_scratch[dev] = ptr;
+  }
+  char* base = static_cast<char*>(g_static_scratch[dev]);
+  const int64_t n_pix = (int64_t)f.n_rows * f.n_cols;
+  Slot s;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    void* q = bytes ? base + off : nullptr;
+    off += bytes;
+    return q;
+  };
+  s.pairs = static_cast<float4*>(carve(L.pairs));
+  s.rowgeo = static_cast<float4*>(carve(L.geo));
+  s.fd = static_cast<float*>(carve(L.fd));
+  s.pixc = static_cast<float4*>(carve(L.pixc));
+  s.fbase = static_cast<float*>(carve(L.fbase));
+  s.partials = static_cast<float2*>(carve(L.partials));
+  s.partial_cap = n_kb > 1 ? (int64_t)n_kb * n_pix : 0;
+  s.mask = static_cast<unsigned long long*>(carve(L.mask));
+  s.det_cell = static_cast<rc_detection*>(carve(L.det_cell));
+  s.staging = g_static_geo;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  Prepared prep;
+  st = prepare_frame(&shape, s, f, nullptr, hs, &prep);
+  if (st != RC_OK) return st;
+  // 0: geometry rows from the host staging
+  RC_HIP(hipMemcpyAsync(s.rowgeo, g_static_geo, (size_t)prep.up.n16 * 16, hipMemcpyHostToDevice, hs));
+  // 1: range compression (or the given spectrum) into the interpolation table
+  if (prep.raw_in) {
+    rc::RangeMulti m;
+    m.f[m.n_frames++] = prep.ra;
+    RC_HIP(rc::launch_range_compress(m, hs));
+  } else {
+    rc::PairMulti m;
+    m.f[m.n_frames++] = prep.pa;
+    RC_HIP(rc::launch_spectrum_pairs(m, hs));
+  }
+  // 2: pixel tables
+  {
+    rc::TableMulti m;
+    m.f[m.n_frames++] = prep.ta;
+    RC_HIP(rc::launch_pixel_tables(m, hs));
+  }
+  if (f.doppler_out)
+    RC_HIP(hipMemcpyAsync(f.doppler_out, s.fd, (size_t)n_pix * sizeof(float), hipMemcpyDeviceToDevice, hs));
+  // 3: back-projection, and the sum of the chirp blocks' partial images
+  {
+    rc::BpBatch b{};
+    b.chg = prep.chg;
+    b.sums = 1;
+    b.form = shape.d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
+             : shape.d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
+    rc::BpFrame bf = prep.bf;
+    bf.chunk = (bf.n_kb * bf.n_tiles + 7) / 8;
+    bf.slot_base = 0;
+    b.f[b.n_frames++] = bf;
+    b.n_slots = bf.chunk;
+    RC_HIP(rc::launch_backproject(b, hs));
+    if (bf.n_kb > 1) {
+      rc::ReduceBatch rb{};
+      rb.f[rb.n_frames++] = rc::ReduceFrame{bf.out, s.image_used, n_pix, bf.n_kb};
+      RC_HIP(rc::launch_reduce_partials(rb, hs));
+    }
+  }
+  // 4: CA-CFAR and ordered compaction into the caller's buffers
+  const rc_plan_desc& d = shape.d;
+  const int h = d.cfar_guard + d.cfar_train;
+  const int n_train = (2 * h + 1) * (2 * h + 1) - (2 * d.cfar_guard + 1) * (2 * d.cfar_guard + 1);
+  const double alpha = n_train * (std::pow(d.cfar_pfa, -1.0 / n_train) - 1.0);
+  const int wpr = (f.n_cols + 63) / 64;
+  {
+    rc::CfarMulti m;
+    m.f[m.n_frames++] = rc::CfarArgs{s.image_used, f.n_rows, f.n_cols, d.cfar_guard, d.cfar_train,
+                                     alpha / n_train, d.cfar_margin_rel, s.mask, wpr, s.det_cell, nullptr,
+                                     nullptr, 0};
+    RC_HIP(rc::launch_cfar(m, hs));
+  }
+  {
+    rc::CompactMulti m;
+    m.f[m.n_frames++] = rc::CompactArgs{s.mask, s.det_cell, f.n_rows, f.n_cols, wpr, detections, det_cap, n_det};
+    RC_HIP(rc::launch_compact(m, hs));
+  }
+  return RC_OK;
+}
 
 rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes) {
   rc_status st = validate_desc(desc);

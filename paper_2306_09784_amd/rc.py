@@ -113,7 +113,7 @@ DETECTION_DTYPE = np.dtype([("pixel", "<i4"), ("power", "<f4"), ("threshold", "<
 ENTRY_POINTS = [
     "rc_plan_create", "rc_plan_slot_bytes", "rc_frame_validate", "rc_process_batch", "rc_poll", "rc_detections",
     "rc_image", "rc_stage_times", "rc_frame_release", "rc_plan_destroy", "rc_last_error", "rc_grid_cartesian",
-    "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar",
+    "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar", "rc_process_frame_static",
 ]
 
 
@@ -154,6 +154,7 @@ def _load():
                                     C.c_double, i32, vp]),
         "rc_resample_polar": (C.c_int, [vp, i32, i32, C.c_double, C.c_double, C.c_double, C.c_double,
                                         C.c_double, C.c_double, vp, i64, vp, vp]),
+        "rc_process_frame_static": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(rc_frame), vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -262,6 +263,21 @@ def validate_frame(cfg: PlanConfig, frame) -> int:
     under a plan of this configuration (host only, no GPU)."""
     d = cfg.desc()
     return lib.rc_frame_validate(C.byref(d), C.byref(frame))
+
+
+#: device scratch the no-allocation entry point works in (RC_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def process_frame_static(cfg: PlanConfig, frame, detections, n_det, stream=None) -> None:
+    """rc_process_frame_static: one frame through the pipeline with no
+    allocation.  detections: device tensor of DETECTION_DTYPE records (any
+    shape, its byte size / 16 is the capacity); n_det: device int64 tensor of
+    one element."""
+    d = cfg.desc()
+    cap = detections.numel() * detections.element_size() // 16 if detections is not None else 0
+    check(lib.rc_process_frame_static(C.byref(d), C.byref(frame), _ptr(detections), cap, _ptr(n_det),
+                                      _stream_handle(stream)), "rc_process_frame_static")
 
 
 def _ptr(t) -> Optional[int]:

@@ -248,3 +248,33 @@ def test_benchmark_frames_pass_the_phase_range_guard(rc):
                   n_channels_max=CH, n_pix_max=16)
         assert rc.validate_frame(pc, fr) == rc.RC_OK, (name, rc.last_error())
 
+
+def test_static_entry_point_refuses_before_any_device_call(rc):
+    """rc_process_frame_static works in RC_STATIC_SCRATCH_BYTES of device
+    memory it never allocates: a frame whose table alone exceeds it (1024
+    chirps x 8 channels x 512 bins x 16 B = 64 MiB), a plan with the recheck,
+    and missing outputs are refused on the host, before any HIP call."""
+    M, CH, NB = 1024, 8, 512
+    q = np.zeros((M, CH, 2), np.float32)
+    vel = np.zeros((M, 2), np.float32)
+    dummy = np.zeros(16, np.float32)
+    img = np.zeros(32, np.float32)
+    cfg = _cfg(rc, n_samples_max=1024, n_fft_max=2048, n_bins_max=NB, n_chirps_max=M, n_channels_max=CH,
+               n_pix_max=16)
+    fr = rc.Plan.make_frame(1, data=dummy, q_tx=q, q_rx=q.copy(), vel=vel, pixels=dummy, n_rows=4, n_cols=4,
+                            n_bins=NB, n_fft=2048, fs=1024 / synth.RADAR["t_chirp"], n_samples=1024,
+                            image_out=img)
+    det = np.zeros(64, np.float32)
+    cnt = np.zeros(1, np.int64)
+    with pytest.raises(rc.RcError) as ei:
+        rc.process_frame_static(cfg, fr, None, None, 0)
+    assert ei.value.status == rc.RC_EINVAL
+    import ctypes as C
+    d = cfg.desc()
+    st = rc.lib.rc_process_frame_static(C.byref(d), C.byref(fr), det.ctypes.data, 4, cnt.ctypes.data, None)
+    assert st == rc.RC_EINVAL and "scratch" in rc.last_error()
+    assert rc.STATIC_SCRATCH_BYTES == 32 << 20
+    small = _cfg(rc, max_rechecks=8)
+    d = small.desc()
+    st = rc.lib.rc_process_frame_static(C.byref(d), C.byref(fr), det.ctypes.data, 4, cnt.ctypes.data, None)
+    assert st == rc.RC_EINVAL and "recheck" in rc.last_error()
