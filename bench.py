@@ -230,6 +230,75 @@ def cpu_full_frame(frame, pix, n_rows, n_cols, procs: int = 16):
                 os.environ[key] = v
 
 
+def form_outputs(rc, synth, torch, frame, precision):
+    """One frame in one precision form: its spectrum (before w_sar), image and
+    detections, on the host."""
+    dev = torch.device("cuda:0")
+    cfg = frame.cfg
+    n_pix = frame.n_rows * frame.n_cols
+    raw = torch.from_numpy(frame.raw).to(dev)
+    pix = torch.from_numpy(np.ascontiguousarray(frame.pix)).to(dev)
+    img = torch.empty((n_pix, 2), dtype=torch.float32, device=dev)
+    spec = torch.empty((cfg.n_chirps, cfg.n_channels, frame.n_bins, 2), dtype=torch.float32, device=dev)
+    pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
+                       n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
+                       n_pix_max=n_pix, max_detections=1 << 16, precision=precision, cfar_margin_rel=1e-2)
+    with rc.Plan(pc) as plan:
+        f = rc.Plan.make_frame(1, data=raw, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
+                               n_rows=frame.n_rows, n_cols=frame.n_cols, n_bins=frame.n_bins, n_fft=frame.n_fft,
+                               fs=frame.fs, n_samples=cfg.n_samples, image_out=img, spectrum_out=spec,
+                               height=cfg.height)
+        plan.process([f])
+        dets = plan.detections(1)
+        plan.release(1)
+    torch.cuda.synchronize()
+    return {"spectrum": spec.cpu().numpy().view(np.complex64)[..., 0], "image": img.cpu().numpy().view(np.complex64)
+            .reshape(-1), "detections": dets}
+
+
+def oracle_errors(frame, forms, workload, n_pixels=300):
+    """Per-stage error of every precision form against the FP64 oracle (part of
+    the oracle's leg of the benchmark): the spectrum's relative L2 error over
+    all rows, the image's max |dP| / max |P| on n_pixels sampled pixels and the
+    brightest ones, and the detection list against the oracle's list of the
+    whole image (stored by tests/golden/make_full_detections.py for this
+    frame), as cells that differ and how many of them lie outside 1 % of the
+    oracle's threshold."""
+    import oracle as O
+    from paper_2306_09784_amd import synth
+
+    R = synth.RADAR
+    k = O.radar_constants(R["f0"], R["bandwidth"], R["t_chirp"], frame.fs, frame.n_fft)
+    s = O.range_compress(frame.raw, O.window("hann", frame.cfg.n_samples), frame.n_fft, frame.n_bins)
+    rng = np.random.default_rng(91)
+    any_img = next(iter(forms.values()))["image"]
+    idx = np.unique(np.concatenate([rng.integers(0, any_img.size, n_pixels), np.argsort(-np.abs(any_img))[:50]]))
+    pix = frame.pix.astype(np.float64)[idx]
+    fd = O.doppler_table(pix, frame.q_tx, frame.q_rx, frame.vel, k["kd"])
+    P = O.bp_alg2(pix, frame.q_tx, frame.q_rx, fd, s, O.window("hann", frame.cfg.n_chirps), k["a1"], k["a2"])
+    gold = None
+    path = os.path.join(ROOT, "tests", "golden", f"full_detections_{workload}.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            gold = json.load(f)
+    out = {}
+    for name, o in forms.items():
+        e = {"spectrum_rel_l2": float(np.linalg.norm(o["spectrum"] - s) / np.linalg.norm(s)),
+             "image_max_rel": float(np.abs(o["image"][idx].astype(np.complex128) - P).max() / np.abs(P).max())}
+        if gold is not None:
+            g = set(int(c) for c in o["detections"]["pixel"])
+            ol = set(int(d[0]) for d in gold["detections"])
+            near = {int(c): (p, t) for c, p, t in gold["near"]}
+            diff = g ^ ol
+            e["detections"] = len(g)
+            e["oracle_detections"] = len(ol)
+            e["detections_differing"] = len(diff)
+            e["differing_beyond_1pct_of_threshold"] = sum(
+                1 for c in diff if c not in near or abs(near[c][0] - near[c][1]) > 1e-2 * near[c][1])
+        out[name] = e
+    return out
+
+
 def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, steps, warmup,
                   doppler=0, want_image=False, depth=2, n_streams=None, plan_kw=None, upload=False):
     """Times `steps` frames through rc_process_batch + rc_detections, `depth`
@@ -562,11 +631,16 @@ def _target_gain_db(img, pix, targets, ref_img, ref_pix, rad=0.06):
 
 def ablation(rc, synth, torch, steps=5, warmup=5):
     """The measures of the paper's Tab. II on one synthetic frame of its
-    reference setting (1024 chirps x 16 RX, 30 m x 30 m): Alg. 1 on the 2.5 cm
-    Cartesian grid (reference), then the Doppler table (Alg. 2), the polar grid
-    (Sec. III-E), 8 of the 16 RX (Sec. III-F) and all combined.  Reports BP
-    time and its share of the reference, next to the paper's shares, and the
-    mean coherent gain change at the point targets."""
+    reference setting (1024 chirps x 16 RX, 30 m x 30 m): Alg. 1 as stated on
+    the 2.5 cm Cartesian grid (reference: metres and seconds, tau, f_hyp in Hz
+    and its division by df per term), then its constants folded (row 3,
+    "Opt.", Sec. III-C), the Doppler table (Alg. 2, Sec. III-D), the polar grid
+    (Sec. III-E), 8 of the 16 RX (Sec. III-F) and all combined.  Row 2 (the
+    chirp window as a vector instead of a per-pixel, per-chirp weight, Sec.
+    III-B) has no measurement here: the per-pixel window is not defined, so
+    every row already uses the vector.  Reports BP time and its share of the
+    reference, next to the paper's shares, and the mean coherent gain change at
+    the point targets."""
     cfg = synth.CONFIGS["paper-ref"]
     frame = synth.make_frame(cfg, device="cuda")
     q = np.concatenate([frame.q_tx.reshape(-1, 2), frame.q_rx.reshape(-1, 2)])
@@ -578,14 +652,15 @@ def ablation(rc, synth, torch, steps=5, warmup=5):
                           "q_rx": np.ascontiguousarray(frame.q_rx[:, :8]),
                           "cfg": synth.dataclasses.replace(cfg, n_rx=8)})
     runs = {
-        "ref_alg1_cartesian_16rx": (frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_EXACT),
+        "ref_alg1_cartesian_16rx": (frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_EXACT_DIRECT),
+        "opt_constants": (frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_EXACT),
         "doppler_table": (frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_AVERAGE),
         "polar_grid": (frame, polar, g["nth"], g["nr"], rc.RC_DOPPLER_AVERAGE),
         "rx_8": (half, frame.pix, frame.n_rows, frame.n_cols, rc.RC_DOPPLER_AVERAGE),
         "combined": (half, polar, g["nth"], g["nr"], rc.RC_DOPPLER_AVERAGE),
     }
-    paper = {"doppler_table": (63.7, 65.0), "polar_grid": (11.9, 10.4), "rx_8": (51.7, 52.6),
-             "combined": (2.9, 2.4)}
+    paper = {"opt_constants": (83.7, 70.5), "doppler_table": (63.7, 65.0), "polar_grid": (11.9, 10.4),
+             "rx_8": (51.7, 52.6), "combined": (2.9, 2.4)}
     out, ref_ms, ref_img = {}, None, None
     for name, (fr, pix, nr, nc, dop) in runs.items():
         run = time_pipeline(rc, synth, torch, fr, pix, nr, nc, rc.RC_PREC_FP32, steps, warmup, doppler=dop,
@@ -600,6 +675,8 @@ def ablation(rc, synth, torch, steps=5, warmup=5):
                                                                frame.pix),
                      "region_snr_db": _region_snr_db(run["image"], pix, frame.targets),
                      "pixels": nr * nc}
+    out["row2_w_sar_vector"] = ("not measured: the per-pixel, per-chirp window of the initial reference is not "
+                                "defined in the paper; every row uses the chirp window as a vector")
     return out
 
 
@@ -618,7 +695,10 @@ def make_sensors(rc, synth, torch, n_sensors, seed=3000):
 
 
 def mixed_plan_config(rc, synth, sensors, slots, **kw):
+    """Plan for the mixed-size sensors; serving runs the split-phase form, whose
+    detection lists match the FP64 oracle's outside the CFAR band."""
     frs = [s.frame for s in sensors]
+    kw.setdefault("precision", rc.RC_PREC_FP32_SPLIT)
     return rc.PlanConfig(radar=synth.RADAR, n_samples_max=max(f.cfg.n_samples for f in frs),
                          n_fft_max=max(f.n_fft for f in frs), n_bins_max=max(f.n_bins for f in frs),
                          n_chirps_max=max(f.cfg.n_chirps for f in frs),
@@ -673,7 +753,8 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=F
     finally:
         srv.close()
     terms = sum(s.frame.n_rows * s.frame.n_cols * s.frame.cfg.n_chirps * s.frame.cfg.n_channels for s in order)
-    out = {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "frames_per_s": n_frames / wall,
+    out = {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "precision": "fp32-split",
+           "frames_per_s": n_frames / wall,
            "bp_terms_per_s_incl_all_stages": terms / wall, "wall_s": wall, "inputs": (
                "beat cubes resident in HBM" if resident else "beat cubes uploaded from pinned host memory")}
     if not resident:
@@ -697,6 +778,7 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
     finally:
         srv.close()
     res["load"] = load
+    res["precision"] = "fp32-split"
     res["realtime_bound_ms"] = 1024 * synth.RADAR["t_pri"] * 1e3
     return res
 
@@ -874,16 +956,27 @@ def main(argv=None):
         },
         "synth_s": t_synth,
     }
+    forms_out = {}
     if not args.main_only:
-        # the same frame with the split-phase (high-accuracy) form
-        sp = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                           rc.RC_PREC_FP32_SPLIT, max(5, args.steps // 2), args.warmup)
-        sp1 = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                            rc.RC_PREC_FP32_SPLIT, 10, args.warmup, depth=1)
-        out["split_phase_form"] = {
-            "frames_per_s": sp["fps"], "backprojection_ms": float(sp1["stages"][:, 2].mean()),
-            "p99_ms": 1e3 * float(np.percentile(sp1["lat"], 99))}
-        progress("split-phase form done")
+        # the same frame in every precision form: split-phase back-projection
+        # (oracle-matching detections) and the matrix-core spectrum forms
+        out["precision_forms"] = {"fp32": {"frames_per_s": out["value"], "range_ms": range_ms, "backprojection_ms": bp_ms,
+                                           "p99_ms": out["resident_p99_ms"]}}
+        for name, prec in (("fp32-split", rc.RC_PREC_FP32_SPLIT), ("fp16-spectrum", rc.RC_PREC_FP16),
+                           ("bf16-spectrum", rc.RC_PREC_BF16)):
+            sp = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, prec,
+                               max(5, args.steps // 2), args.warmup)
+            sp1 = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, prec, 10,
+                                args.warmup, depth=1)
+            out["precision_forms"][name] = {
+                "frames_per_s": sp["fps"], "range_ms": float(sp1["stages"][:, 0].mean()),
+                "backprojection_ms": float(sp1["stages"][:, 2].mean()),
+                "p99_ms": 1e3 * float(np.percentile(sp1["lat"], 99)),
+                "vs_fp32_frames_per_s": sp["fps"] / out["value"]}
+        for name, prec in (("fp32", rc.RC_PREC_FP32), ("fp32-split", rc.RC_PREC_FP32_SPLIT),
+                           ("fp16-spectrum", rc.RC_PREC_FP16), ("bf16-spectrum", rc.RC_PREC_BF16)):
+            forms_out[name] = form_outputs(rc, synth, torch, frame, prec)
+        progress("precision forms done")
         # the same frame with the double-precision recheck of near-threshold cells
         rk = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, rc.RC_PREC_FP32, 5,
                            args.warmup, depth=1, plan_kw=dict(max_rechecks=4096))
@@ -919,6 +1012,9 @@ def main(argv=None):
             progress("serving done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_budget)
+        if forms_out:
+            out["errors_vs_oracle"] = oracle_errors(frame, forms_out, args.workload)
+            progress("per-stage errors done")
         # the small frame and the paper's configuration, each timed whole
         full = {}
         small = synth.make_frame(synth.CONFIGS["plain-small"], device="cuda")

@@ -64,8 +64,18 @@ typedef enum rc_precision {
   RC_PREC_FP32 = 0,
   /* Single precision with the phase split into a per-pixel reference path
    * (evaluated in double) plus a small single-precision difference; keeps the
-   * carrier phase accurate to ~1e-5 of a turn. */
-  RC_PREC_FP32_SPLIT = 1
+   * carrier phase accurate to ~1e-5 of a turn.  Its detection lists match the
+   * FP64 oracle's outside the CFAR band; the plain form's carry its ~1e-4
+   * turns of phase rounding at weak cells beside strong scatterers. */
+  RC_PREC_FP32_SPLIT = 1,
+  /* Reduced-precision spectrum: range compression (the beat spectrum s of
+   * Sec. III-C) on the matrix cores, its two DFT stages as complex matrix
+   * products with FP16 (RC_PREC_FP16) or BF16 (RC_PREC_BF16) operands, FP32
+   * accumulation and twiddles split into high and low parts; back-projection
+   * as RC_PREC_FP32_SPLIT.  DFT lengths 256 .. 4096 with n_samples at most
+   * n_fft / 2 (RC_EINVAL otherwise). */
+  RC_PREC_FP16 = 2,
+  RC_PREC_BF16 = 3
 } rc_precision;
 
 typedef enum rc_doppler_mode {
@@ -75,7 +85,16 @@ typedef enum rc_doppler_mode {
   /* Alg. 1: the radial velocity of every pixel, chirp and channel from that
    * chirp's velocity (the paper's reference before the simplification).
    * Single precision only (not with RC_PREC_FP32_SPLIT). */
-  RC_DOPPLER_EXACT = 1
+  RC_DOPPLER_EXACT = 1,
+  /* Alg. 1 as the paper states it, before its constants are folded
+   * (Sec. III-C, Tab. II "Opt."): metres and seconds, tau = (d_tx + d_rx) / c,
+   * f_hyp = mu tau + f0 v / c in Hz, the interpolation index f_hyp / df and
+   * the phase f0 tau, each a division or product per term; the radial speeds
+   * <p - q, v> / d divided out per leg.  The same values as RC_DOPPLER_EXACT
+   * to single-precision rounding (its phase holds ~2e-3 turns of it at 30 m),
+   * slower: the reference row of the ablation.  Single precision only, no
+   * continuous SAR. */
+  RC_DOPPLER_EXACT_DIRECT = 2
 } rc_doppler_mode;
 
 /* Continuous SAR (the paper's conclusion, Sec. V: a continuous measurement

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librc.so")
 ARCH = os.environ.get("RC_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["staging.hip", "range.hip", "tables.hip", "bp.hip", "cfar.hip", "recheck.hip", "resample.hip",
+SOURCES = ["staging.hip", "range.hip", "range_mfma.hip", "tables.hip", "bp.hip", "cfar.hip", "recheck.hip", "resample.hip",
            "sliding.hip", "runtime.hip"]
 
 # Packed FP32 instructions are disabled for all device code (they are never

@@ -1,5 +1,7 @@
 // Back-projection core: Alg. 2 of the paper (Sec. IV), single precision; the
-// exact-Doppler form evaluates Alg. 1 (Sec. II) for the ablation of Sec. III-D.
+// exact-Doppler form evaluates Alg. 1 (Sec. II) for the ablation of Sec. III-D,
+// and the direct form evaluates Alg. 1 as the paper states it, before the
+// constants of Sec. III-C are folded (the reference of Tab. II's "Opt." row).
 //
 // For every pixel p the lane evaluates, for each chirp m and channel ch,
 //   d_hyp = |p - q_tx(m,ch)| + |p - q_rx(m,ch)|,
@@ -107,6 +109,12 @@ __device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p, const P
     const float x = p.x - q.x, y = p.y - q.y;
     l.d = __builtin_amdgcn_sqrtf(fmaf(x, x, fmaf(y, y, p.z)));  // p.z: squared antenna height
     l.dop = fmaf(x, q.z, y * q.w) * __builtin_amdgcn_rcpf(l.d);
+  } else if constexpr (FORM == kBpDirect) {
+    // metres and metres per second: the distance and the radial speed
+    // <p - q, v> / d (a division, as Alg. 1 writes it)
+    const float x = p.x - q.x, y = p.y - q.y;
+    l.d = sqrtf(fmaf(x, x, fmaf(y, y, p.z)));
+    l.dop = fmaf(x, q.z, y * q.w) / l.d;
   } else if constexpr (FORM == kBpSplit) {
     const float n = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
     if constexpr (SERIES) {
@@ -143,7 +151,7 @@ struct Stage {
 template <int CHG, int FORM, bool CHECKED, int SUMS, bool SERIES = false>
 __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int row_end, const float4 p,
                                          const float fidx, float (&out_re)[SUMS], float (&out_im)[SUMS]) {
-  constexpr bool EXACT = FORM == kBpExact;
+  constexpr bool EXACT = FORM == kBpExact || FORM == kBpDirect;
   constexpr int U = CHG < 4 ? CHG : 4;
   constexpr int UPG = CHG / U;  // stages per TX group
   const float nbm1 = (float)(a.n_bins - 1);
@@ -201,6 +209,13 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
         const float d_hyp = tx.d + rx.d;
         f = fmaf(a.a1, d_hyp, tx.dop + rx.dop);
         turn = d_hyp;
+      } else if constexpr (FORM == kBpDirect) {
+        // Alg. 1: tau = (d_tx + d_rx) / c, f_hyp = mu tau + f0 v / c in Hz, its
+        // bin f_hyp / df, and the carrier phase f0 tau in turns
+        const float tau = (tx.d + rx.d) / a.lit_c;
+        const float f_hyp = fmaf(a.lit_mu, tau, a.lit_f0 * (tx.dop + rx.dop) / a.lit_c);
+        f = f_hyp / a.lit_df;
+        turn = a.lit_f0 * tau;
       } else {
         const float d_hyp = tx.d + rx.d;
         f = fmaf(a.a1, d_hyp, fb);
@@ -330,7 +345,7 @@ __device__ __forceinline__ float box_max_dist(float px, float py, float lx, floa
 template <int CHG, int FORM, int SUMS>
 __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   constexpr bool SPLIT = FORM == kBpSplit;
-  constexpr bool EXACT = FORM == kBpExact;
+  constexpr bool EXACT = FORM == kBpExact || FORM == kBpDirect;
   const int w = blockIdx.x;
   const int xcd = w & 7;
   const int slot = w >> 3;
@@ -378,7 +393,8 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
                     box_max_dist(p.x, p.y, a.rx_lo_x, a.rx_lo_y, a.rx_hi_x, a.rx_hi_y, a.h2);
   const float flo = fmaf(a.a1, dlo, fdp), fhi = fmaf(a.a1, dhi, fdp);
   const float mg = a.f_margin + a.f_slack;
-  const bool inside = (flo >= mg) & (fhi <= (float)(a.n_bins - 1) - mg);
+  // (the direct form keeps metres and runs the range-tested loop throughout)
+  const bool inside = FORM != kBpDirect && (flo >= mg) & (fhi <= (float)(a.n_bins - 1) - mg);
 
   // chirp block kb covers chirps [m0, m1), i.e. rows [m0 n_ch, m1 n_ch)
   const int m0 = __builtin_amdgcn_readfirstlane((int)(((int64_t)kb * a.n_chirps) / a.n_kb));
@@ -434,12 +450,16 @@ __global__ __launch_bounds__(kThreads) void reduce_partials_kernel(ReduceBatch b
 
 template <int CHG, int SUMS>
 void launch_form(const BpBatch& b, dim3 grid, hipStream_t s) {
-  if (b.form == kBpSplit)
+  if (b.form == kBpSplit) {
     hipLaunchKernelGGL((bp_kernel<CHG, kBpSplit, SUMS>), grid, dim3(kThreads), 0, s, b);
-  else if (b.form == kBpExact)
+  } else if (b.form == kBpExact) {
     hipLaunchKernelGGL((bp_kernel<CHG, kBpExact, SUMS>), grid, dim3(kThreads), 0, s, b);
-  else
+  } else if (b.form == kBpDirect) {
+    // (launch_backproject admits the direct form with single sums only)
+    if constexpr (SUMS == 1) hipLaunchKernelGGL((bp_kernel<CHG, kBpDirect, 1>), grid, dim3(kThreads), 0, s, b);
+  } else {
     hipLaunchKernelGGL((bp_kernel<CHG, kBpPlain, SUMS>), grid, dim3(kThreads), 0, s, b);
+  }
 }
 
 template <int CHG>
@@ -489,7 +509,7 @@ int bp_chirp_blocks(int64_t n_rows, int64_t n_cols, int n_chirps, int n_ch, int 
 
 hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
   if (b.n_frames < 1 || b.n_frames > kBpMaxFrames || b.n_slots < 1 || b.chg < 1 || b.form < kBpPlain ||
-      b.form > kBpExact || (b.sums != 1 && b.sums != 3))
+      b.form > kBpDirect || (b.sums != 1 && b.sums != 3) || (b.form == kBpDirect && b.sums != 1))
     return hipErrorInvalidValue;
   int slots = 0;
   for (int i = 0; i < b.n_frames; ++i) {
@@ -497,7 +517,8 @@ hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
     int tx, nt;
     bp_tiles(f.n_rows, f.n_cols, &tx, &nt);
     if (f.n_rows < 1 || f.n_cols < 1 || f.n_chirps < 1 || f.n_ch < 1 || f.n_bins < 2 || f.n_ch % b.chg != 0 ||
-        (b.form == kBpExact && (!f.rowv || !f.grpv)) || (b.form != kBpExact && (!f.rowq || !f.grpq)) ||
+        ((b.form == kBpExact || b.form == kBpDirect) && (!f.rowv || !f.grpv)) ||
+        (b.form != kBpExact && b.form != kBpDirect && (!f.rowq || !f.grpq)) ||
         (b.sums == 3 && (!f.roww || (reinterpret_cast<uintptr_t>(f.roww) & 7))) || !f.out ||
         f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.slot_base != slots ||
         f.chunk != (f.n_kb * nt + 7) / 8 ||

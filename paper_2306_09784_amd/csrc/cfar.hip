@@ -166,9 +166,17 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m
     if (threadIdx.x == kCompactThreads - 1) base_sh = pos;  // the last thread ends the sweep
     __syncthreads();
     const int64_t end = base_sh < a.cap ? base_sh : a.cap;
-    for (int64_t i = base + threadIdx.x; i < end; i += kCompactThreads) a.det_out[i] = a.det_cell[a.det_out[i].pixel];
+    const int64_t hend = base_sh < a.host_cap ? base_sh : a.host_cap;
+    for (int64_t i = base + threadIdx.x; i < end; i += kCompactThreads) {
+      const rc_detection d = a.det_cell[a.det_out[i].pixel];
+      a.det_out[i] = d;
+      if (i < hend) a.host_out[i] = d;
+    }
   }
-  if (threadIdx.x == 0) *a.count = base_sh;
+  if (threadIdx.x == 0) {
+    *a.count = base_sh;
+    if (a.host_count) *a.host_count = base_sh;
+  }
 }
 
 }  // namespace
@@ -198,7 +206,8 @@ hipError_t launch_compact(const CompactMulti& m, hipStream_t s) {
   if (m.n_frames < 1 || m.n_frames > CompactMulti::kMax) return hipErrorInvalidValue;
   for (int i = 0; i < m.n_frames; ++i) {
     const CompactArgs& a = m.f[i];
-    if (a.words_per_row != (a.n_cols + kTileCols - 1) / kTileCols || a.n_rows < 0 || a.cap < 0)
+    if (a.words_per_row != (a.n_cols + kTileCols - 1) / kTileCols || a.n_rows < 0 || a.cap < 0 ||
+        a.host_cap < 0 || a.host_cap > a.cap || (a.host_cap > 0 && !a.host_out))
       return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)m.n_frames), dim3(kCompactThreads), 0, s, m);

@@ -58,6 +58,14 @@ struct RangeArgs {
 using RangeMulti = Multi<RangeArgs, 32>;
 hipError_t launch_range_compress(const RangeMulti& m, hipStream_t s);
 
+// The same table from range compression on the matrix cores (FP16 or BF16
+// operands, FP32 accumulation, split twiddles; range_mfma.hip).  Takes DFT
+// lengths kRangeMfmaMinFft .. kRangeMfmaMaxFft with n_s <= n_fft / 2.
+constexpr int kRangeMfmaMinFft = 256;
+constexpr int kRangeMfmaMaxFft = 4096;
+bool range_mfma_supported(int n_fft, int n_s);
+hipError_t launch_range_mfma(const RangeMulti& m, bool bf16, hipStream_t s);
+
 // Caller-supplied spectrum -> interpolation table (same layout as above).
 struct PairArgs {
   const float2* spec;     // [rows][n_bins]
@@ -78,7 +86,8 @@ hipError_t launch_spectrum_pairs(const PairMulti& m, hipStream_t s);
 //    corr = (R^2 - pp) / R, the first-order path correction (in turns) for
 //    the rounding of pp that back-projection adds to every two-way path;
 //  * exact-Doppler form: (P'.x, P'.y, h^2, corr) with corr = 2 <P, P - P'> / R,
-//    the first-order correction for the rounding of P itself.
+//    the first-order correction for the rounding of P itself; the direct form
+//    (exact == 2) the same in metres.
 struct TableArgs {
   const float2* pix;
   int64_t n_pix;
@@ -92,7 +101,7 @@ struct TableArgs {
   // split-phase form: pixc = (P'.x, P'.y, R, frac(2R)) with R = |P| and
   // fbase = a1 * 2R + f_doppler (the index of the reference path 2R)
   int split;
-  int exact;
+  int exact;                      // 1: exact-Doppler form, 2: direct form (metres)
   double a1;                      // bins per wavelength of path
   float* fbase;                   // [n_pix] (split only)
   double height;                  // antennas above the pixel plane, metres
@@ -148,11 +157,14 @@ struct BpFrame {
   float f_slack;          // largest |Doppler index| a term can carry (exact form)
   float h2;               // (antenna height / wavelength)^2 (0: planar geometry)
   float q_max;            // largest antenna distance from the aperture centre (wavelengths)
+  // direct form (Alg. 1 as stated): rows and pixels in metres, velocities in
+  // m/s, and the constants it divides by and multiplies with
+  float lit_c, lit_mu, lit_f0, lit_df;
 };
 
 constexpr int kBpMaxFrames = 16;  // frames per launch (descriptors travel as kernel arguments)
 
-enum BpForm { kBpPlain = 0, kBpSplit = 1, kBpExact = 2 };
+enum BpForm { kBpPlain = 0, kBpSplit = 1, kBpExact = 2, kBpDirect = 3 };
 
 struct BpBatch {
   int chg, form, n_frames, n_slots;  // n_slots: per-XCD slots (grid = 8 n_slots)
@@ -286,6 +298,12 @@ struct CompactArgs {
   rc_detection* det_out;
   int64_t cap;
   int64_t* count;
+  // optional: the count and the first host_cap records also go straight to
+  // mapped, coherent pinned host memory (device addresses), so no copy is
+  // needed to read them on the host
+  int64_t* host_count;
+  rc_detection* host_out;
+  int64_t host_cap;
 };
 using CompactMulti = Multi<CompactArgs, 32>;
 hipError_t launch_compact(const CompactMulti& m, hipStream_t s);

@@ -47,6 +47,12 @@ constexpr int kDetPrefix = 1024;  // detections copied back asynchronously per f
 // to 2^16 turns)
 constexpr double kMaxPathTurns = 65536.0;
 
+// back-projection in the split-phase form: RC_PREC_FP32_SPLIT and the
+// reduced-precision spectrum forms
+bool split_phase(const rc_plan_desc& d) { return d.precision != RC_PREC_FP32; }
+// range compression on the matrix cores (FP16 / BF16 operands)
+bool mfma_spectrum(const rc_plan_desc& d) { return d.precision == RC_PREC_FP16 || d.precision == RC_PREC_BF16; }
+
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int64_t v) {
   int r = 0;
@@ -107,8 +113,10 @@ struct Slot {
   // through staging_dev)
   float* staging = nullptr;
   const float4* staging_dev = nullptr;
-  int64_t* h_count = nullptr;
-  rc_detection* h_det = nullptr;
+  int64_t* h_count = nullptr;        // mapped, coherent: the compaction kernel writes
+  rc_detection* h_det = nullptr;      // the count and the first records here
+  int64_t* h_count_dev = nullptr;     // (their device addresses)
+  rc_detection* h_det_dev = nullptr;
   hipEvent_t done = nullptr;
   hipEvent_t stage_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // state
@@ -216,7 +224,7 @@ SlotSizes slot_sizes(const rc_plan_desc& d) {
   s.geo = round_up(geo_floats(d) * sizeof(float));
   s.fd = round_up((size_t)d.n_pix_max * sizeof(float));
   s.pixc = round_up((size_t)d.n_pix_max * sizeof(float4));
-  s.fbase = d.precision == RC_PREC_FP32_SPLIT ? round_up((size_t)d.n_pix_max * sizeof(float)) : 0;
+  s.fbase = split_phase(d) ? round_up((size_t)d.n_pix_max * sizeof(float)) : 0;
   s.partials = round_up((size_t)partial_capacity(d) * sizeof(float2));
   s.image = round_up((size_t)d.n_pix_max * sizeof(float2));
   s.mask = round_up((size_t)d.n_pix_max * sizeof(unsigned long long));
@@ -256,12 +264,15 @@ rc_status validate_desc(const rc_plan_desc* d) {
   if (d->cfar_margin_rel < 0) return fail(RC_EINVAL, "cfar_margin_rel must be >= 0");
   if (d->max_rechecks < 0 || d->max_rechecks > (1 << 20))
     return fail(RC_EINVAL, "max_rechecks must be in [0, 2^20]");
-  if (d->precision != RC_PREC_FP32 && d->precision != RC_PREC_FP32_SPLIT)
+  if (d->precision != RC_PREC_FP32 && d->precision != RC_PREC_FP32_SPLIT && d->precision != RC_PREC_FP16 &&
+      d->precision != RC_PREC_BF16)
     return fail(RC_EINVAL, "unknown precision %d", (int)d->precision);
-  if (d->doppler != RC_DOPPLER_AVERAGE && d->doppler != RC_DOPPLER_EXACT)
+  if (d->doppler != RC_DOPPLER_AVERAGE && d->doppler != RC_DOPPLER_EXACT && d->doppler != RC_DOPPLER_EXACT_DIRECT)
     return fail(RC_EINVAL, "unknown Doppler mode %d", (int)d->doppler);
-  if (d->doppler == RC_DOPPLER_EXACT && d->precision != RC_PREC_FP32)
-    return fail(RC_EINVAL, "the exact-Doppler form is single precision only");
+  if (d->doppler != RC_DOPPLER_AVERAGE && d->precision != RC_PREC_FP32)
+    return fail(RC_EINVAL, "the exact-Doppler forms are single precision only");
+  if (d->doppler == RC_DOPPLER_EXACT_DIRECT && d->sliding_sensors > 0)
+    return fail(RC_EINVAL, "the direct form of Alg. 1 does not form continuous-SAR apertures");
   for (rc_window_kind k : {d->range_window, d->sar_window})
     if (k != RC_WIN_RECT && k != RC_WIN_HANN && k != RC_WIN_KAISER)
       return fail(RC_EINVAL, "unknown window kind %d", (int)k);
@@ -348,7 +359,7 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
       if (!std::isfinite(f.w_sar[m]))
         return fail(RC_EINVAL, "frame %lld: non-finite w_sar", (long long)f.frame_id);
   }
-  if (f.f_doppler && d.doppler == RC_DOPPLER_EXACT)
+  if (f.f_doppler && d.doppler != RC_DOPPLER_AVERAGE)
     return fail(RC_EINVAL, "frame %lld: f_doppler with RC_DOPPLER_EXACT (Alg. 1 has no Doppler table)",
                 (long long)f.frame_id);
   if (f.sliding != RC_SLIDE_OFF) {
@@ -370,6 +381,11 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
       return fail(RC_EINVAL, "frame %lld: n_fft %d must be a power of two in [max(4, n_samples), %d]", (long long)f.frame_id, f.n_fft, d.n_fft_max);
     if (f.n_bins > f.n_fft)
       return fail(RC_EINVAL, "frame %lld: n_bins %d > n_fft %d", (long long)f.frame_id, f.n_bins, f.n_fft);
+    if (mfma_spectrum(d) && !rc::range_mfma_supported(f.n_fft, f.n_samples))
+      return fail(RC_EINVAL,
+                  "frame %lld: the matrix-core spectrum takes DFT lengths %d..%d with n_samples <= n_fft / 2 "
+                  "(n_fft %d, n_samples %d)", (long long)f.frame_id, rc::kRangeMfmaMinFft, rc::kRangeMfmaMaxFft,
+                  f.n_fft, f.n_samples);
   } else if (f.input_kind == RC_INPUT_SPECTRUM) {
     if (f.n_fft < f.n_bins || f.n_fft < 1)
       return fail(RC_EINVAL, "frame %lld: n_fft %d must be >= n_bins (it defines the bin spacing)", (long long)f.frame_id, f.n_fft);
@@ -388,7 +404,7 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
   // n_bins - 1 for a caller's table (the documented bound on its values).
   // Longer paths need the split-phase form, whose phase never holds the
   // whole path.
-  if (d.precision != RC_PREC_FP32_SPLIT) {
+  if (!split_phase(d)) {
     const double c = d.radar.c > 0 ? d.radar.c : 299792458.0;
     const double df = f.fs / f.n_fft;
     const double a1 = d.radar.bandwidth / d.radar.t_chirp / (c * df);  // bins per metre of path
@@ -474,24 +490,29 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
     x = (float)((q[0] - cen_x) * inv_lam);
     y = (float)((q[1] - cen_y) * inv_lam);
   };
-  const bool exact = d.doppler == RC_DOPPLER_EXACT;
+  const bool exact = d.doppler == RC_DOPPLER_EXACT || d.doppler == RC_DOPPLER_EXACT_DIRECT;
+  const bool direct = d.doppler == RC_DOPPLER_EXACT_DIRECT;
   double vmax = 0;
   double q_max = 0;  // largest antenna distance from the aperture centre, wavelengths
   for (int64_t r = 0; r < rows; ++r) {
     float x, y;
     // exact form: positions and kd v(m) (bins per unit radial speed)
     const int64_t m = r / f.n_channels;
-    const float kvx = (float)(kd * f.vel[2 * m]), kvy = (float)(kd * f.vel[2 * m + 1]);
+    // the direct form keeps metres and m/s (Alg. 1 as stated)
+    const double vs = direct ? 1.0 : kd;
+    const float kvx = (float)(vs * f.vel[2 * m]), kvy = (float)(vs * f.vel[2 * m + 1]);
     local(f.q_rx + 2 * r, x, y);
-    rowq[r] = exact ? make_float4(x, y, kvx, kvy)
-                    : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
+    rowq[r] = direct  ? make_float4((float)(f.q_rx[2 * r] - cen_x), (float)(f.q_rx[2 * r + 1] - cen_y), kvx, kvy)
+              : exact ? make_float4(x, y, kvx, kvy)
+                      : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
     rlx = std::min(rlx, x); rly = std::min(rly, y); rhx = std::max(rhx, x); rhy = std::max(rhy, y);
     q_max = std::max(q_max, std::hypot((double)x, (double)y));
     local(f.q_tx + 2 * r, x, y);
     q_max = std::max(q_max, std::hypot((double)x, (double)y));
     if (r % chg == 0)
-      grpq[r / chg] = exact ? make_float4(x, y, kvx, kvy)
-                            : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
+      grpq[r / chg] = direct ? make_float4((float)(f.q_tx[2 * r] - cen_x), (float)(f.q_tx[2 * r + 1] - cen_y), kvx, kvy)
+                      : exact ? make_float4(x, y, kvx, kvy)
+                              : make_float4(-2.f * x, -2.f * y, (float)((double)x * x + (double)y * y), 0.f);
     tlx = std::min(tlx, x); tly = std::min(tly, y); thx = std::max(thx, x); thy = std::max(thy, y);
     vmax = std::max(vmax, std::hypot((double)f.vel[2 * m], (double)f.vel[2 * m + 1]));
   }
@@ -603,8 +624,8 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   ta.inv_lam = inv_lam;
   ta.fd = s.fd;
   ta.pixc = s.pixc;
-  ta.split = d.precision == RC_PREC_FP32_SPLIT;
-  ta.exact = exact;
+  ta.split = split_phase(d);
+  ta.exact = direct ? 2 : exact ? 1 : 0;
   ta.a1 = a1 * lam;
   ta.fbase = s.fbase;
   ta.height = f.height;
@@ -617,7 +638,7 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   rc::BpFrame& ba = out->bf;
   ba = rc::BpFrame{};
   ba.pixc = s.pixc;
-  ba.fidx = d.precision == RC_PREC_FP32_SPLIT ? s.fbase : s.fd;
+  ba.fidx = split_phase(d) ? s.fbase : s.fd;
   ba.pairs = s.pairs;
   ba.rowq = exact ? nullptr : d_rowq;
   ba.grpq = exact ? nullptr : d_grpq;
@@ -642,6 +663,10 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   ba.f_margin = (float)(1e-3 + 64.0 * f.n_bins * std::ldexp(1.0, -24));
   ba.h2 = (float)(f.height * inv_lam * f.height * inv_lam);
   ba.q_max = (float)(q_max * (1.0 + 1e-6));
+  ba.lit_c = (float)c;
+  ba.lit_mu = (float)mu;
+  ba.lit_f0 = (float)d.radar.f0;
+  ba.lit_df = (float)df;
   if (n_kb > 1 && (int64_t)n_kb * planes * n_pix > s.partial_cap)
     return fail(RC_EINVAL, "frame %lld: %d chirp blocks of %lld pixels exceed the slot's partial buffer",
                 (long long)f.frame_id, n_kb, (long long)n_pix);
@@ -731,17 +756,17 @@ rc_status finish_batch(Plan* p, const std::vector<Slot*>& slot, const rc_frame* 
     rc::CompactMulti m;
     for (int i = i0; i < n && m.n_frames < rc::CompactMulti::kMax; ++i) {
       Slot& s = *slot[i];
+      // the count and the first records go straight to the slot's mapped
+      // pinned memory: no copy per frame
       m.f[m.n_frames++] = rc::CompactArgs{s.mask, s.det_cell, frames[i].n_rows, frames[i].n_cols, wpr(i),
-                                          s.det_out, (int64_t)d.max_detections, s.det_count};
+                                          s.det_out, (int64_t)d.max_detections, s.det_count, s.h_count_dev,
+                                          s.h_det_dev, (int64_t)std::min(kDetPrefix, d.max_detections)};
     }
     RC_HIP(rc::launch_compact(m, st));
   }
-  const int prefix = std::min(kDetPrefix, d.max_detections);
   for (int i = 0; i < n; ++i) {
     Slot& s = *slot[i];
     if (timed) RC_HIP(hipEventRecord(s.stage_ev[4], st));
-    RC_HIP(hipMemcpyAsync(s.h_count, s.det_count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    RC_HIP(hipMemcpyAsync(s.h_det, s.det_out, prefix * sizeof(rc_detection), hipMemcpyDeviceToHost, st));
     RC_HIP(hipEventRecord(s.done, st));
   }
   return RC_OK;
@@ -782,7 +807,7 @@ StaticLayout static_layout(const rc_plan_desc& d, const rc_frame& f, int n_kb) {
   l.geo = round_up(((8 * rows + f.n_chirps + n_s + 3) & ~size_t(3)) * sizeof(float));
   l.fd = round_up(n_pix * sizeof(float));
   l.pixc = round_up(n_pix * sizeof(float4));
-  l.fbase = d.precision == RC_PREC_FP32_SPLIT ? round_up(n_pix * sizeof(float)) : 0;
+  l.fbase = split_phase(d) ? round_up(n_pix * sizeof(float)) : 0;
   l.partials = n_kb > 1 ? round_up((size_t)n_kb * n_pix * sizeof(float2)) : 0;
   l.mask = round_up((size_t)f.n_rows * ((f.n_cols + 63) / 64) * sizeof(unsigned long long));
   l.det_cell = round_up(n_pix * sizeof(rc_detection));
@@ -858,7 +883,8 @@ rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* fram
   if (prep.raw_in) {
     rc::RangeMulti m;
     m.f[m.n_frames++] = prep.ra;
-    RC_HIP(rc::launch_range_compress(m, hs));
+    RC_HIP(mfma_spectrum(shape.d) ? rc::launch_range_mfma(m, shape.d.precision == RC_PREC_BF16, hs)
+                                  : rc::launch_range_compress(m, hs));
   } else {
     rc::PairMulti m;
     m.f[m.n_frames++] = prep.pa;
@@ -877,8 +903,9 @@ rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* fram
     rc::BpBatch b{};
     b.chg = prep.chg;
     b.sums = 1;
-    b.form = shape.d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
-             : shape.d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
+    b.form = shape.d.doppler == RC_DOPPLER_EXACT_DIRECT ? rc::kBpDirect
+             : shape.d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
+             : split_phase(shape.d) ? rc::kBpSplit : rc::kBpPlain;
     rc::BpFrame bf = prep.bf;
     bf.chunk = (bf.n_kb * bf.n_tiles + 7) / 8;
     bf.slot_base = 0;
@@ -906,7 +933,8 @@ rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* fram
   }
   {
     rc::CompactMulti m;
-    m.f[m.n_frames++] = rc::CompactArgs{s.mask, s.det_cell, f.n_rows, f.n_cols, wpr, detections, det_cap, n_det};
+    m.f[m.n_frames++] = rc::CompactArgs{s.mask, s.det_cell, f.n_rows, f.n_cols, wpr, detections, det_cap, n_det,
+                                        nullptr, nullptr, 0};
     RC_HIP(rc::launch_compact(m, hs));
   }
   return RC_OK;
@@ -1026,8 +1054,14 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     }
     if (e == hipSuccess) {
       const size_t hb = 64 + (size_t)std::min(kDetPrefix, desc->max_detections) * sizeof(rc_detection);
-      e = hipHostMalloc(reinterpret_cast<void**>(&s.h_count), hb, hipHostMallocDefault);
-      if (e == hipSuccess) s.h_det = reinterpret_cast<rc_detection*>(reinterpret_cast<char*>(s.h_count) + 64);
+      e = hipHostMalloc(reinterpret_cast<void**>(&s.h_count), hb, hipHostMallocMapped | hipHostMallocCoherent);
+      if (e == hipSuccess) {
+        s.h_det = reinterpret_cast<rc_detection*>(reinterpret_cast<char*>(s.h_count) + 64);
+        void* dev = nullptr;
+        e = hipHostGetDevicePointer(&dev, s.h_count, 0);
+        s.h_count_dev = static_cast<int64_t*>(dev);
+        s.h_det_dev = reinterpret_cast<rc_detection*>(static_cast<char*>(dev) + 64);
+      }
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (desc->stage_timing)
@@ -1148,7 +1182,8 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
           m.f[m.n_frames++] = prep[j].ra;
           done[j] = 1;
         }
-      RC_BATCH(rc::launch_range_compress(m, st));
+      RC_BATCH(mfma_spectrum(p->d) ? rc::launch_range_mfma(m, p->d.precision == RC_PREC_BF16, st)
+                                   : rc::launch_range_compress(m, st));
     }
     rc::PairMulti m;
     for (int i = 0; i < n_frames; ++i) {
@@ -1192,8 +1227,9 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     rc::BpBatch b{};
     b.chg = prep[i].chg;
     b.sums = prep[i].sums;
-    b.form = p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
-             : p->d.precision == RC_PREC_FP32_SPLIT ? rc::kBpSplit : rc::kBpPlain;
+    b.form = p->d.doppler == RC_DOPPLER_EXACT_DIRECT ? rc::kBpDirect
+             : p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
+             : split_phase(p->d) ? rc::kBpSplit : rc::kBpPlain;
     for (int oj = oi; oj < n_frames && b.n_frames < rc::kBpMaxFrames; ++oj) {
       const int j = order[oj];
       if (done[j] || prep[j].chg != prep[i].chg || prep[j].sums != prep[i].sums) continue;

@@ -59,9 +59,12 @@ __global__ __launch_bounds__(kThreads) void pixel_tables_kernel(TableMulti m) {
   const float ppf = (float)pp;
   const double R = sqrt(pp);
   if (a.exact) {
-    const float fx = (float)lx, fy = (float)ly;
-    const double corr = R > 0.0 ? 2.0 * (lx * (lx - fx) + ly * (ly - fy)) / R : 0.0;
-    a.pixc[i] = make_float4(fx, fy, (float)(hl * hl), (float)corr);
+    // exact form: wavelengths; direct form (exact == 2): metres
+    const double u = a.exact == 2 ? 1.0 / a.inv_lam : 1.0;
+    const double mx = lx * u, my = ly * u, mr = R * u, mh = hl * u;
+    const float fx = (float)mx, fy = (float)my;
+    const double corr = mr > 0.0 ? 2.0 * (mx * (mx - fx) + my * (my - fy)) / mr : 0.0;
+    a.pixc[i] = make_float4(fx, fy, (float)(mh * mh), (float)corr);
   } else if (a.split) {
     const double two_r = 2.0 * R;
     a.pixc[i] = make_float4((float)lx, (float)ly, (float)R, (float)(two_r - floor(two_r)));

@@ -26,9 +26,9 @@ STATUS_NAMES = {0: "RC_OK", 1: "RC_EINVAL", 2: "RC_ENOMEM", 3: "RC_ETRUNC", 4: "
 RC_WIN_RECT, RC_WIN_HANN, RC_WIN_KAISER = 0, 1, 2
 WINDOWS = {"rect": RC_WIN_RECT, "hann": RC_WIN_HANN, "kaiser": RC_WIN_KAISER}
 # rc_precision
-RC_PREC_FP32, RC_PREC_FP32_SPLIT = 0, 1
+RC_PREC_FP32, RC_PREC_FP32_SPLIT, RC_PREC_FP16, RC_PREC_BF16 = 0, 1, 2, 3
 # rc_doppler_mode
-RC_DOPPLER_AVERAGE, RC_DOPPLER_EXACT = 0, 1
+RC_DOPPLER_AVERAGE, RC_DOPPLER_EXACT, RC_DOPPLER_EXACT_DIRECT = 0, 1, 2
 # rc_input_kind
 RC_INPUT_RAW, RC_INPUT_SPECTRUM = 0, 1
 # rc_sliding (continuous SAR: sub-apertures of a sensor's chirp stream)

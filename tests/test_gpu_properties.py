@@ -154,12 +154,15 @@ def test_channel_subsets_add_up(rc, torch, frame, seed):
 def test_bp_time_scales_with_pixels_and_channels(rc, torch):
     """Back-projection time is proportional to the pixel count and to the
     channel count (Sec. III-E/F): the median device time of frames with 4x the
-    pixels and 2x the channels is 4x and 2x, within 25 % (1024 x 1024 pixels,
-    128 chirps x 8 channels as the base, 0.5 ms, so that fixed costs are a few
-    per cent; twice the channels share each TX distance among more of them,
-    so that ratio is a little under 2)."""
+    pixels and 2x the channels is 4x and 2x, within 15 % (1024 x 1024 pixels,
+    256 chirps x 8 channels as the base, about 1 ms, so that fixed costs and
+    the launch's ragged end are a few per cent).  Both ratios come out a
+    little low: the larger frames split their chirps into fewer blocks (two
+    instead of four at 2048 x 2048), so they write and sum fewer partial images
+    per term (measured 3.55x and 1.90x), and twice the channels share each TX
+    distance among more of them."""
     def bp_ms(nx, n_rx):
-        cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="scale", n_samples=256, n_chirps=128,
+        cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="scale", n_samples=256, n_chirps=256,
                                   n_rx=n_rx, nx=nx, ny=nx, seed=950)
         fr = synth.make_frame(cfg, device="cuda")
         dev = torch.device("cuda")
@@ -182,5 +185,5 @@ def test_bp_time_scales_with_pixels_and_channels(rc, torch):
     px = bp_ms(2048, 8) / base
     ch = bp_ms(1024, 16) / base
     print(f"bp time ratios: 4x pixels {px:.3f}, 2x channels {ch:.3f}", flush=True)
-    assert 0.75 * 4 <= px <= 1.25 * 4
-    assert 0.75 * 2 <= ch <= 1.25 * 2
+    assert 0.85 * 4 <= px <= 1.15 * 4
+    assert 0.85 * 2 <= ch <= 1.15 * 2
