@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define RC_ABI_VERSION 4
+#define RC_ABI_VERSION 5
 
 typedef enum rc_status {
   RC_OK = 0,
@@ -120,6 +120,24 @@ typedef enum rc_input_kind {
   RC_INPUT_SPECTRUM = 1  /* data = beat spectrum complex64 [n_chirps][n_channels][n_bins]  */
 } rc_input_kind;
 
+/* How a plan holds the device memory of the frames in flight. */
+typedef enum rc_frame_memory {
+  /* Every frame slot sized for the plan's limits and allocated at creation
+   * (hbm_budget_bytes, if set, bounds their total). */
+  RC_MEMORY_SLOTS = 0,
+  /* One device arena of hbm_budget_bytes allocated at creation.  A frame takes
+   * from it the bytes its own sizes need (rc_frame_bytes) when it is admitted
+   * and gives them back when it is released, so frames of uneven sizes share
+   * the budget by what they use: rc_process_batch returns RC_ENOTREADY
+   * (enqueuing nothing) while the batch does not fit what is free, and
+   * RC_ENOMEM for a frame larger than the whole arena (it would never fit);
+   * max_frames_in_flight still bounds the count.  A frame may then hand over
+   * its input in pinned host memory (rc_frame.data_host): the plan copies it
+   * into the frame's share of the arena on the frame's stream before its
+   * kernels (the paper's pinned-memory Load, Sec. IV). */
+  RC_MEMORY_BUDGET = 1
+} rc_frame_memory;
+
 /* Radar constants (Tab. I of the paper for its sensor). */
 typedef struct rc_radar {
   double f0;         /* carrier frequency, Hz (76.6e9)              */
@@ -163,6 +181,7 @@ typedef struct rc_plan_desc {
   int32_t sliding_sensors;      /* sensors 0 .. sliding_sensors - 1                */
   int32_t sliding_subapertures; /* K, sub-apertures per aperture, 1 .. 64          */
   int32_t sliding_depth;        /* sub-apertures of one sensor in flight at once   */
+  rc_frame_memory frame_memory; /* RC_MEMORY_SLOTS (default) or RC_MEMORY_BUDGET     */
 } rc_plan_desc;
 
 /* One radar frame (one synthetic aperture -> one image + detection list).
@@ -213,6 +232,9 @@ typedef struct rc_frame {
                                    computes it from the mean velocity at the
                                    aperture centre (Sec. III-D).  Not with
                                    RC_DOPPLER_EXACT (Alg. 1 has no such table). */
+  const void* data_host;        /* RC_MEMORY_BUDGET only: the input of `data`, in
+                                   pinned host memory, with data = NULL; the plan
+                                   copies it to the device.  NULL otherwise.      */
 } rc_frame;
 
 #define RC_DET_NEAR_THRESHOLD 1u  /* in the band, decided in single precision */
@@ -234,6 +256,13 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out);
 
 /* Bytes of device memory one frame slot of this descriptor needs. */
 rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes);
+
+/* Bytes of device memory one frame (host descriptor, checked as by
+ * rc_frame_validate) takes from the arena of a RC_MEMORY_BUDGET plan with this
+ * descriptor: its interpolation table, geometry, pixel tables, partial images,
+ * image (if image_out is NULL), CFAR buffers, detection list, recheck buffers
+ * and, with data_host, its input.  Host only, no GPU. */
+rc_status rc_frame_bytes(const rc_plan_desc* desc, const rc_frame* frame, int64_t* bytes);
 
 /* Checks one frame (host) against a plan descriptor (host) exactly as
  * rc_process_batch() checks it before enqueuing anything, without a plan or a
@@ -257,7 +286,8 @@ rc_status rc_frame_validate(const rc_plan_desc* desc, const rc_frame* frame);
  * before the call returns (through pinned staging), so they may be reused
  * at once; device inputs must stay valid until the frame completes.
  * Returns RC_ENOTREADY without enqueuing anything when fewer than n_frames
- * slots are free, RC_EINVAL on a frame outside the plan's limits or with
+ * slots are free (or, under RC_MEMORY_BUDGET, fewer bytes of the arena than
+ * the batch needs), RC_EINVAL on a frame outside the plan's limits or with
  * inconsistent sizes.  Kernel contributions whose interpolation index lies
  * outside [0, n_bins - 1] are zero, not an error. */
 rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -125,6 +126,10 @@ struct Slot {
   int32_t n_rows = 0, n_cols = 0;
   int32_t sensor = -1;        // continuous-SAR sensor of the frame in the slot, or -1
   float2* image_used = nullptr;
+  // RC_MEMORY_BUDGET: the frame's share of the plan's arena and, for a frame
+  // handed over in pinned host memory, its input copied there
+  size_t arena_off = 0, arena_len = 0;
+  void* input = nullptr;
 };
 
 // A sensor's continuous-SAR stream: sub-aperture b's partial images live in
@@ -165,7 +170,42 @@ struct Plan {
   float2* ring = nullptr;
   int n_ring = 0, planes = 0;
   int64_t ring_stride = 0;  // complex values per ring slot
+  // RC_MEMORY_BUDGET: one device arena, handed out first fit in 256-byte
+  // units; free_list maps the offset of each free range to its length
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  std::map<size_t, size_t> free_list;
 };
+
+// First fit from the arena; returns the offset or SIZE_MAX when no free range holds len.
+size_t arena_alloc(Plan* p, size_t len) {
+  for (auto it = p->free_list.begin(); it != p->free_list.end(); ++it) {
+    if (it->second < len) continue;
+    const size_t off = it->first, rest = it->second - len;
+    p->free_list.erase(it);
+    if (rest) p->free_list.emplace(off + len, rest);
+    return off;
+  }
+  return SIZE_MAX;
+}
+
+// Returns a range to the arena, merging it with free neighbours.
+void arena_free(Plan* p, size_t off, size_t len) {
+  if (!len) return;
+  auto next = p->free_list.lower_bound(off);
+  if (next != p->free_list.end() && off + len == next->first) {
+    len += next->second;
+    next = p->free_list.erase(next);
+  }
+  if (next != p->free_list.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += len;
+      return;
+    }
+  }
+  p->free_list.emplace(off, len);
+}
 
 int sliding_planes(const rc_plan_desc& d) { return d.sar_window == RC_WIN_HANN ? 3 : 1; }
 int sliding_ring(const rc_plan_desc& d) { return d.sliding_subapertures + d.sliding_depth - 1; }
@@ -176,10 +216,10 @@ size_t ring_bytes(const rc_plan_desc& d) {
 
 struct SlotSizes {
   size_t pairs, geo, fd, pixc, fbase, partials, image, mask, det_cell, det_out, listed, rpower, spec64, need,
-      plist, pmap;
+      plist, pmap, input = 0;
   size_t total() const {
     return pairs + geo + fd + pixc + fbase + partials + image + mask + det_cell + det_out + listed + rpower +
-           spec64 + need + plist + pmap + 64;
+           spec64 + need + plist + pmap + input + 64;
   }
 };
 
@@ -189,6 +229,12 @@ int window_cells(const rc_plan_desc& d) {
 }
 
 size_t round_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Detection records a frame can produce: at most one per pixel, and the
+// plan's max_detections are kept.
+int64_t det_capacity(const rc_plan_desc& d, const rc_frame& f) {
+  return std::min<int64_t>(d.max_detections, (int64_t)f.n_rows * f.n_cols);
+}
 
 // Pixel-blocks of partial images a slot may need: a frame of W waves (64
 // lanes each, covering at least its n_pix pixels) is split into
@@ -240,6 +286,68 @@ SlotSizes slot_sizes(const rc_plan_desc& d) {
   return s;
 }
 
+// The device bytes of one frame under RC_MEMORY_BUDGET: the buffers of a slot
+// sized for this frame (n_kb chirp blocks of `planes` partial images), plus its
+// input when it comes from pinned host memory.
+SlotSizes frame_sizes(const rc_plan_desc& d, const rc_frame& f, int n_kb, int planes) {
+  SlotSizes s;
+  const size_t rows = (size_t)f.n_chirps * f.n_channels;
+  const size_t n_pix = (size_t)f.n_rows * f.n_cols;
+  const size_t n_s = f.input_kind == RC_INPUT_RAW ? (size_t)f.n_samples : 0;
+  const bool rk = d.max_rechecks > 0 && f.sliding == RC_SLIDE_OFF;
+  const size_t metres = rk ? recheck_floats(rows, f.n_chirps, n_s) : f.sliding != RC_SLIDE_OFF ? 2 * rows : 0;
+  s.pairs = round_up(rows * f.n_bins * sizeof(float4));
+  s.geo = round_up(((rows * 8 + metres + f.n_chirps + n_s + 3) & ~size_t(3)) * sizeof(float));
+  s.fd = round_up(n_pix * sizeof(float));
+  s.pixc = round_up(n_pix * sizeof(float4));
+  s.fbase = split_phase(d) ? round_up(n_pix * sizeof(float)) : 0;
+  s.partials = n_kb > 1 ? round_up((size_t)n_kb * planes * n_pix * sizeof(float2)) : 0;
+  s.image = f.image_out ? 0 : round_up(n_pix * sizeof(float2));
+  s.mask = round_up(n_pix * sizeof(unsigned long long));
+  s.det_cell = round_up(n_pix * sizeof(rc_detection));
+  s.det_out = round_up((size_t)det_capacity(d, f) * sizeof(rc_detection));
+  s.listed = rk ? round_up((size_t)d.max_rechecks * sizeof(int)) : 0;
+  s.rpower = rk ? round_up((size_t)d.max_rechecks * window_cells(d) * sizeof(double)) : 0;
+  s.need = rk ? round_up(n_pix * sizeof(unsigned long long)) : 0;
+  s.plist = rk ? round_up((size_t)d.max_rechecks * window_cells(d) * sizeof(int)) : 0;
+  s.pmap = rk ? round_up(n_pix * sizeof(int)) : 0;
+  s.spec64 = rk ? round_up(rows * f.n_bins * sizeof(double2)) : 0;
+  s.input = f.data_host ? round_up(rows * (f.input_kind == RC_INPUT_RAW ? (size_t)f.n_samples : (size_t)f.n_bins) *
+                                   sizeof(float2))
+                        : 0;
+  return s;
+}
+
+// Points a slot's device buffers into [base, base + sz.total()).
+void carve_slot(Slot& s, char* base, const SlotSizes& sz) {
+  size_t off = 0;
+  auto take = [&](size_t n) -> char* {
+    char* q = n ? base + off : nullptr;
+    off += n;
+    return q;
+  };
+  s.pairs = reinterpret_cast<float4*>(take(sz.pairs));
+  s.rowgeo = reinterpret_cast<float4*>(take(sz.geo));
+  s.fd = reinterpret_cast<float*>(take(sz.fd));
+  s.pixc = reinterpret_cast<float4*>(take(sz.pixc));
+  s.fbase = reinterpret_cast<float*>(take(sz.fbase));
+  s.partials = reinterpret_cast<float2*>(take(sz.partials));
+  s.image = reinterpret_cast<float2*>(take(sz.image));
+  s.mask = reinterpret_cast<unsigned long long*>(take(sz.mask));
+  s.det_cell = reinterpret_cast<rc_detection*>(take(sz.det_cell));
+  s.det_out = reinterpret_cast<rc_detection*>(take(sz.det_out));
+  s.listed = reinterpret_cast<int*>(take(sz.listed));
+  s.rpower = reinterpret_cast<double*>(take(sz.rpower));
+  s.need = reinterpret_cast<unsigned long long*>(take(sz.need));
+  s.plist = reinterpret_cast<int*>(take(sz.plist));
+  s.pmap = reinterpret_cast<int*>(take(sz.pmap));
+  s.spec64 = reinterpret_cast<double2*>(take(sz.spec64));
+  s.input = take(sz.input);
+  s.det_count = reinterpret_cast<int64_t*>(take(64));
+  s.n_listed = reinterpret_cast<int*>(s.det_count + 1);
+  s.n_need = s.n_listed + 1;
+}
+
 rc_status validate_desc(const rc_plan_desc* d) {
   if (!d) return fail(RC_EINVAL, "desc is NULL");
   if (d->abi_version != RC_ABI_VERSION)
@@ -271,6 +379,10 @@ rc_status validate_desc(const rc_plan_desc* d) {
     return fail(RC_EINVAL, "unknown Doppler mode %d", (int)d->doppler);
   if (d->doppler != RC_DOPPLER_AVERAGE && d->precision != RC_PREC_FP32)
     return fail(RC_EINVAL, "the exact-Doppler forms are single precision only");
+  if (d->frame_memory != RC_MEMORY_SLOTS && d->frame_memory != RC_MEMORY_BUDGET)
+    return fail(RC_EINVAL, "unknown frame_memory %d", (int)d->frame_memory);
+  if (d->frame_memory == RC_MEMORY_BUDGET && d->hbm_budget_bytes <= 0)
+    return fail(RC_EINVAL, "RC_MEMORY_BUDGET needs hbm_budget_bytes > 0");
   if (d->doppler == RC_DOPPLER_EXACT_DIRECT && d->sliding_sensors > 0)
     return fail(RC_EINVAL, "the direct form of Alg. 1 does not form continuous-SAR apertures");
   for (rc_window_kind k : {d->range_window, d->sar_window})
@@ -289,8 +401,8 @@ rc_status validate_desc(const rc_plan_desc* d) {
   return RC_OK;
 }
 
-void free_slot(Slot& s) {
-  if (s.pairs) (void)hipFree(s.pairs);
+void free_slot(Slot& s, bool owns_device) {
+  if (owns_device && s.pairs) (void)hipFree(s.pairs);
   if (s.staging) (void)hipHostFree(s.staging);
   if (s.h_count) (void)hipHostFree(s.h_count);
   if (s.done) (void)hipEventDestroy(s.done);
@@ -301,7 +413,8 @@ void free_slot(Slot& s) {
 
 void free_plan(Plan* p) {
   if (!p) return;
-  for (Slot& s : p->slots) free_slot(s);
+  for (Slot& s : p->slots) free_slot(s, !p->arena);
+  if (p->arena) (void)hipFree(p->arena);
   for (Sensor& s : p->sensors)
     if (s.done) (void)hipEventDestroy(s.done);
   if (p->ring) (void)hipFree(p->ring);
@@ -342,8 +455,11 @@ rc_status validate_frame(const Plan* p, const rc_frame& f) {
     return fail(RC_EINVAL, "frame %lld: n_rows %d too large", (long long)f.frame_id, f.n_rows);
   if (!(f.fs > 0)) return fail(RC_EINVAL, "frame %lld: fs must be positive", (long long)f.frame_id);
   if (!std::isfinite(f.height)) return fail(RC_EINVAL, "frame %lld: height must be finite", (long long)f.frame_id);
-  if (!f.data || !f.q_tx || !f.q_rx || !f.vel || !f.pixels)
+  if (!(f.data || f.data_host) || !f.q_tx || !f.q_rx || !f.vel || !f.pixels)
     return fail(RC_EINVAL, "frame %lld: data, q_tx, q_rx, vel and pixels are required", (long long)f.frame_id);
+  if (f.data_host && (f.data || d.frame_memory != RC_MEMORY_BUDGET))
+    return fail(RC_EINVAL, "frame %lld: data_host (with data NULL) needs a RC_MEMORY_BUDGET plan",
+                (long long)f.frame_id);
   const int64_t rows = (int64_t)f.n_chirps * f.n_channels;
   for (int64_t i = 0; i < 2 * rows; ++i)
     if (!std::isfinite(f.q_tx[i]) || !std::isfinite(f.q_rx[i]))
@@ -759,8 +875,8 @@ rc_status finish_batch(Plan* p, const std::vector<Slot*>& slot, const rc_frame* 
       // the count and the first records go straight to the slot's mapped
       // pinned memory: no copy per frame
       m.f[m.n_frames++] = rc::CompactArgs{s.mask, s.det_cell, frames[i].n_rows, frames[i].n_cols, wpr(i),
-                                          s.det_out, (int64_t)d.max_detections, s.det_count, s.h_count_dev,
-                                          s.h_det_dev, (int64_t)std::min(kDetPrefix, d.max_detections)};
+                                          s.det_out, det_capacity(d, frames[i]), s.det_count, s.h_count_dev,
+                                          s.h_det_dev, std::min<int64_t>(kDetPrefix, det_capacity(d, frames[i]))};
     }
     RC_HIP(rc::launch_compact(m, st));
   }
@@ -828,6 +944,7 @@ rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* fram
   const rc_frame& f = *frame;
   if (desc->max_rechecks != 0 || desc->sliding_sensors != 0 || f.sliding != RC_SLIDE_OFF)
     return fail(RC_EINVAL, "the static entry point has no double-precision recheck and no continuous SAR");
+  if (f.data_host || !f.data) return fail(RC_EINVAL, "the static entry point takes its input on the device (data)");
   if (!f.image_out) return fail(RC_EINVAL, "frame %lld: image_out is required", (long long)f.frame_id);
   if (!n_det || det_cap < 0 || (det_cap > 0 && !detections))
     return fail(RC_EINVAL, "detections, det_cap and n_det must describe a device buffer and a device count");
@@ -948,6 +1065,21 @@ rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes) {
   return RC_OK;
 }
 
+rc_status rc_frame_bytes(const rc_plan_desc* desc, const rc_frame* frame, int64_t* bytes) {
+  g_err.clear();
+  rc_status st = validate_desc(desc);
+  if (st != RC_OK) return st;
+  if (!frame || !bytes) return fail(RC_EINVAL, "frame and bytes are required");
+  Plan shape;  // the descriptor's limits only: nothing is allocated
+  shape.d = *desc;
+  shape.planes = desc->sliding_sensors > 0 ? sliding_planes(*desc) : 0;
+  st = validate_frame(&shape, *frame);
+  if (st != RC_OK) return st;
+  const int planes = frame->sliding != RC_SLIDE_OFF ? shape.planes : 1;
+  *bytes = (int64_t)round_up(frame_sizes(*desc, *frame, frame_chirp_blocks(&shape, *frame), planes).total());
+  return RC_OK;
+}
+
 rc_status rc_frame_validate(const rc_plan_desc* desc, const rc_frame* frame) {
   g_err.clear();
   rc_status st = validate_desc(desc);
@@ -968,7 +1100,9 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
   const SlotSizes sz = slot_sizes(*desc);
   const size_t per_slot = sz.total();
   const size_t tw64_bytes = desc->max_rechecks > 0 ? (size_t)desc->n_fft_max / 2 * sizeof(double2) : 0;
-  const size_t need = per_slot * desc->max_frames_in_flight + tw64_bytes + ring_bytes(*desc);
+  const size_t need = desc->frame_memory == RC_MEMORY_BUDGET
+                          ? tw64_bytes + ring_bytes(*desc) + 256
+                          : per_slot * desc->max_frames_in_flight + tw64_bytes + ring_bytes(*desc);
   if (desc->hbm_budget_bytes > 0 && need > (size_t)desc->hbm_budget_bytes)
     return fail(RC_ENOMEM, "plan needs %zu bytes of device memory, budget is %lld", need,
                 (long long)desc->hbm_budget_bytes);
@@ -1016,36 +1150,30 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
   }
   p->slots.resize(desc->max_frames_in_flight);
   const size_t geo_bytes = geo_floats(*desc) * sizeof(float);
-  for (Slot& s : p->slots) {
-    char* base = nullptr;
-    e = hipMalloc(&base, per_slot);
+  const bool budget_mode = desc->frame_memory == RC_MEMORY_BUDGET;
+  if (budget_mode) {
+    // one arena: what the budget leaves after the recheck's twiddles and the
+    // continuous-SAR ring
+    p->arena_bytes = (size_t)desc->hbm_budget_bytes - tw64_bytes - ring_bytes(*desc);
+    e = hipMalloc(&p->arena, p->arena_bytes);
     if (e != hipSuccess) {
       free_plan(p);
-      return fail(RC_ENOMEM, "device allocation of %zu bytes per slot failed: %s", per_slot,
-                  hipGetErrorString(e));
+      return fail(RC_ENOMEM, "device arena of %zu bytes: %s", p->arena_bytes, hipGetErrorString(e));
     }
-    size_t off = 0;
-    auto take = [&](size_t n) { char* q = base + off; off += n; return q; };
-    s.pairs = reinterpret_cast<float4*>(take(sz.pairs));
-    s.rowgeo = reinterpret_cast<float4*>(take(sz.geo));
-    s.fd = reinterpret_cast<float*>(take(sz.fd));
-    s.pixc = reinterpret_cast<float4*>(take(sz.pixc));
-    s.fbase = sz.fbase ? reinterpret_cast<float*>(take(sz.fbase)) : nullptr;
-    s.partials = reinterpret_cast<float2*>(take(sz.partials));
-    s.partial_cap = partial_capacity(*desc);
-    s.image = reinterpret_cast<float2*>(take(sz.image));
-    s.mask = reinterpret_cast<unsigned long long*>(take(sz.mask));
-    s.det_cell = reinterpret_cast<rc_detection*>(take(sz.det_cell));
-    s.det_out = reinterpret_cast<rc_detection*>(take(sz.det_out));
-    s.listed = sz.listed ? reinterpret_cast<int*>(take(sz.listed)) : nullptr;
-    s.rpower = sz.rpower ? reinterpret_cast<double*>(take(sz.rpower)) : nullptr;
-    s.need = sz.need ? reinterpret_cast<unsigned long long*>(take(sz.need)) : nullptr;
-    s.plist = sz.plist ? reinterpret_cast<int*>(take(sz.plist)) : nullptr;
-    s.pmap = sz.pmap ? reinterpret_cast<int*>(take(sz.pmap)) : nullptr;
-    s.spec64 = sz.spec64 ? reinterpret_cast<double2*>(take(sz.spec64)) : nullptr;
-    s.det_count = reinterpret_cast<int64_t*>(take(64));
-    s.n_listed = reinterpret_cast<int*>(s.det_count + 1);
-    s.n_need = s.n_listed + 1;
+    p->free_list.emplace(0, p->arena_bytes);
+  }
+  for (Slot& s : p->slots) {
+    if (!budget_mode) {
+      char* base = nullptr;
+      e = hipMalloc(&base, per_slot);
+      if (e != hipSuccess) {
+        free_plan(p);
+        return fail(RC_ENOMEM, "device allocation of %zu bytes per slot failed: %s", per_slot,
+                    hipGetErrorString(e));
+      }
+      carve_slot(s, base, sz);
+      s.partial_cap = partial_capacity(*desc);
+    }
     e = hipHostMalloc(reinterpret_cast<void**>(&s.staging), geo_bytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) {
       void* dev = nullptr;
@@ -1140,10 +1268,36 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   }
   std::vector<Slot*> slot(n_frames, nullptr);
   std::vector<Prepared> prep(n_frames);
+  // RC_MEMORY_BUDGET: every frame's own bytes from the arena, or nothing at all
+  const bool budget = p->arena != nullptr;
+  std::vector<std::pair<size_t, size_t>> taken;  // (offset, length) per frame
+  std::vector<SlotSizes> fsz(budget ? n_frames : 0);
+  if (budget) {
+    size_t wanted = 0;
+    for (int i = 0; i < n_frames; ++i) {
+      const int planes = frames[i].sliding != RC_SLIDE_OFF ? p->planes : 1;
+      fsz[i] = frame_sizes(p->d, frames[i], frame_chirp_blocks(p, frames[i]), planes);
+      const size_t len = round_up(fsz[i].total());
+      if (len > p->arena_bytes) {  // would never fit, however many frames complete
+        for (const auto& t : taken) arena_free(p, t.first, t.second);
+        return fail(RC_ENOMEM, "frame %lld needs %zu bytes, more than the plan's whole arena of %zu",
+                    (long long)frames[i].frame_id, len, p->arena_bytes);
+      }
+      wanted += len;
+      const size_t off = arena_alloc(p, len);
+      if (off == SIZE_MAX) {
+        for (const auto& t : taken) arena_free(p, t.first, t.second);
+        return fail(RC_ENOTREADY, "the batch needs %zu bytes of the HBM budget (frame %lld: %zu), more than is free",
+                    wanted, (long long)frames[i].frame_id, len);
+      }
+      taken.emplace_back(off, len);
+    }
+  }
   auto undo = [&](rc_status r) {  // a failed batch leaves no slot busy and no stream advanced
     (void)hipStreamSynchronize(st);
     for (Slot* q : slot)
-      if (q) { q->busy = false; q->frame_id = -1; q->sensor = -1; }
+      if (q) { q->busy = false; q->frame_id = -1; q->sensor = -1; q->arena_len = 0; q->input = nullptr; }
+    for (const auto& t : taken) arena_free(p, t.first, t.second);
     return r;
   };
 #define RC_BATCH(call)                                                                  \
@@ -1157,9 +1311,24 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   for (int i = 0; i < n_frames; ++i) {
     for (Slot& c : p->slots)
       if (!c.busy) { slot[i] = &c; break; }
-    rc_status r = prepare_frame(p, *slot[i], frames[i], slide[i].sensor >= 0 ? &slide[i] : nullptr, st, &prep[i]);
+    rc_frame f = frames[i];
+    if (budget) {
+      Slot& q = *slot[i];
+      carve_slot(q, p->arena + taken[i].first, fsz[i]);
+      q.arena_off = taken[i].first;
+      q.arena_len = taken[i].second;
+      const int planes = f.sliding != RC_SLIDE_OFF ? p->planes : 1;
+      q.partial_cap = (int64_t)frame_chirp_blocks(p, f) * planes * f.n_rows * f.n_cols;
+      if (f.data_host) f.data = q.input;  // the plan's copy of the input
+    }
+    rc_status r = prepare_frame(p, *slot[i], f, slide[i].sensor >= 0 ? &slide[i] : nullptr, st, &prep[i]);
     if (r != RC_OK) return undo(r);
   }
+  // inputs handed over in pinned host memory: copied into the frames' arena
+  // shares ahead of their kernels (the paper's pinned Load)
+  for (int i = 0; i < n_frames; ++i)
+    if (frames[i].data_host)
+      RC_BATCH(hipMemcpyAsync(slot[i]->input, frames[i].data_host, fsz[i].input, hipMemcpyHostToDevice, st));
   // 0: every frame's geometry from its staging buffer, one launch per 32 frames
   for (int i0 = 0; i0 < n_frames; i0 += rc::UploadMulti::kMax) {
     rc::UploadMulti m;
@@ -1383,6 +1552,11 @@ rc_status rc_frame_release(void* plan, int64_t frame_id) {
   s->busy = false;
   s->frame_id = -1;
   s->sensor = -1;
+  if (p->arena) {
+    arena_free(p, s->arena_off, s->arena_len);
+    s->arena_len = 0;
+    s->input = nullptr;
+  }
   return RC_OK;
 }
 

@@ -16,7 +16,7 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librc.so")
 
-RC_ABI_VERSION = 4
+RC_ABI_VERSION = 5
 
 # rc_status
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_ETRUNC, RC_EHIP, RC_ENOTREADY, RC_ENOTFOUND = range(7)
@@ -29,6 +29,7 @@ WINDOWS = {"rect": RC_WIN_RECT, "hann": RC_WIN_HANN, "kaiser": RC_WIN_KAISER}
 RC_PREC_FP32, RC_PREC_FP32_SPLIT, RC_PREC_FP16, RC_PREC_BF16 = 0, 1, 2, 3
 # rc_doppler_mode
 RC_DOPPLER_AVERAGE, RC_DOPPLER_EXACT, RC_DOPPLER_EXACT_DIRECT = 0, 1, 2
+RC_MEMORY_SLOTS, RC_MEMORY_BUDGET = 0, 1
 # rc_input_kind
 RC_INPUT_RAW, RC_INPUT_SPECTRUM = 0, 1
 # rc_sliding (continuous SAR: sub-apertures of a sensor's chirp stream)
@@ -70,6 +71,7 @@ class rc_plan_desc(C.Structure):
         ("sliding_sensors", C.c_int32),
         ("sliding_subapertures", C.c_int32),
         ("sliding_depth", C.c_int32),
+        ("frame_memory", C.c_int),
     ]
 
 
@@ -98,6 +100,7 @@ class rc_frame(C.Structure):
         ("sliding", C.c_int),
         ("w_sar", C.c_void_p),
         ("f_doppler", C.c_void_p),
+        ("data_host", C.c_void_p),
     ]
 
 
@@ -111,7 +114,7 @@ DETECTION_DTYPE = np.dtype([("pixel", "<i4"), ("power", "<f4"), ("threshold", "<
 
 #: every entry point declared in include/rc.h
 ENTRY_POINTS = [
-    "rc_plan_create", "rc_plan_slot_bytes", "rc_frame_validate", "rc_process_batch", "rc_poll", "rc_detections",
+    "rc_plan_create", "rc_plan_slot_bytes", "rc_frame_bytes", "rc_frame_validate", "rc_process_batch", "rc_poll", "rc_detections",
     "rc_image", "rc_stage_times", "rc_frame_release", "rc_plan_destroy", "rc_last_error", "rc_grid_cartesian",
     "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar", "rc_process_frame_static",
 ]
@@ -138,6 +141,7 @@ def _load():
         "rc_plan_create": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(C.c_void_p)]),
         "rc_plan_slot_bytes": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(C.c_int64)]),
         "rc_frame_validate": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(rc_frame)]),
+        "rc_frame_bytes": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(rc_frame), C.POINTER(C.c_int64)]),
         "rc_process_batch": (C.c_int, [vp, C.POINTER(rc_frame), i32, vp]),
         "rc_poll": (C.c_int, [vp, i64]),
         "rc_detections": (C.c_int, [vp, i64, C.POINTER(rc_detection), i64, C.POINTER(C.c_int64)]),
@@ -238,6 +242,7 @@ class PlanConfig:
     sliding_sensors: int = 0
     sliding_subapertures: int = 1
     sliding_depth: int = 1
+    frame_memory: int = RC_MEMORY_SLOTS
 
     def desc(self) -> rc_plan_desc:
         r = self.radar
@@ -248,7 +253,7 @@ class PlanConfig:
             WINDOWS[self.range_window], self.range_kaiser_beta, WINDOWS[self.sar_window],
             self.sar_kaiser_beta, self.precision, self.doppler, self.cfar_guard, self.cfar_train, self.cfar_pfa,
             self.cfar_margin_rel, self.max_rechecks, self.hbm_budget_bytes, int(self.stage_timing),
-            self.sliding_sensors, self.sliding_subapertures, self.sliding_depth)
+            self.sliding_sensors, self.sliding_subapertures, self.sliding_depth, self.frame_memory)
 
 
 def slot_bytes(cfg: PlanConfig) -> int:
@@ -263,6 +268,15 @@ def validate_frame(cfg: PlanConfig, frame) -> int:
     under a plan of this configuration (host only, no GPU)."""
     d = cfg.desc()
     return lib.rc_frame_validate(C.byref(d), C.byref(frame))
+
+
+def frame_bytes(cfg: PlanConfig, frame) -> int:
+    """rc_frame_bytes: the device bytes the frame takes from a RC_MEMORY_BUDGET
+    plan of this configuration (host only)."""
+    d = cfg.desc()
+    out = C.c_int64()
+    check(lib.rc_frame_bytes(C.byref(d), C.byref(frame), C.byref(out)), "rc_frame_bytes")
+    return out.value
 
 
 #: device scratch the no-allocation entry point works in (RC_STATIC_SCRATCH_BYTES)
@@ -331,10 +345,12 @@ class Plan:
                    n_samples: int = 0, input_kind: int = RC_INPUT_RAW, image_out=None,
                    doppler_out=None, spectrum_out=None, sensor_id: int = 0, height: float = 0.0,
                    sliding: int = RC_SLIDE_OFF, w_sar: Optional[np.ndarray] = None,
-                   f_doppler=None) -> rc_frame:
+                   f_doppler=None, data_host=None) -> rc_frame:
         """Builds an rc_frame.  q_tx, q_rx, vel (and w_sar, if given) must be
         C-contiguous float32 host arrays that stay alive until rc_process_batch
-        returns; f_doppler is a device tensor of one float per pixel."""
+        returns; f_doppler is a device tensor of one float per pixel;
+        data_host (a pinned host tensor) replaces data in a plan of
+        RC_MEMORY_BUDGET (pass data=None)."""
         for a in (q_tx, q_rx, vel) + ((w_sar,) if w_sar is not None else ()):
             if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags.c_contiguous):
                 raise TypeError("q_tx, q_rx, vel and w_sar must be C-contiguous float32 numpy arrays")
@@ -347,7 +363,7 @@ class Plan:
                         _ptr(data), q_tx.ctypes.data, q_rx.ctypes.data, vel.ctypes.data,
                         _ptr(pixels), n_rows, n_cols, _ptr(image_out), _ptr(doppler_out),
                         _ptr(spectrum_out), float(height), int(sliding),
-                        w_sar.ctypes.data if w_sar is not None else None, _ptr(f_doppler))
+                        w_sar.ctypes.data if w_sar is not None else None, _ptr(f_doppler), _ptr(data_host))
 
     def process(self, frames, stream=None) -> int:
         arr = (rc_frame * len(frames))(*frames)

@@ -7,10 +7,17 @@ slot (the paper's pinned-memory "Load", Sec. IV), enqueues the admitted frames
 as one batch on one of several HIP streams, so batches overlap on the GPU, and
 harvests completed frames (detections on the host) as they finish.
 
-Admission is bounded by HBM: the number of frame slots is the HBM budget
-divided by the device bytes of one slot (``rc_plan_slot_bytes``) plus the
-device input buffer of one frame.  A frame that arrives while every slot is
-busy waits in a FIFO queue; its latency counts from its arrival.
+Admission is bounded by HBM.  With a plan of ``RC_MEMORY_BUDGET`` (the
+server's ``hbm_budget_bytes``), the library holds one device arena of that size
+and admits each frame by the bytes its own sizes need (``rc_frame_bytes``:
+table, pixel tables, partial images, detection buffers and the beat cube,
+which the library copies from the sensor's pinned host memory itself), so
+small frames do not pay for the largest one; a batch that does not fit what is
+free is not enqueued (``RC_ENOTREADY``) and waits.  Without a budget, the
+plan's fixed slots (each sized for the largest frame) bound the frames in
+flight and the server copies each cube into a per-slot device buffer.  A frame
+that cannot be admitted waits in a FIFO queue; its latency counts from its
+arrival.
 
 All compute runs in librc's kernels; this module only moves buffers, keeps
 the clock and does the bookkeeping.
@@ -60,12 +67,15 @@ class Server:
         self.plan = _rc.Plan(plan_cfg)
         self.n_slots = plan_cfg.max_frames_in_flight
         self.resident = resident
+        # a budget plan takes each cube from pinned host memory itself
+        self.by_bytes = plan_cfg.frame_memory == _rc.RC_MEMORY_BUDGET
         dev = torch.device("cuda")
         n_in = plan_cfg.n_chirps_max * plan_cfg.n_channels_max * plan_cfg.n_samples_max
         # device input buffer per slot (the raw cube is copied in from pinned
-        # memory), unless every sensor's cube is already resident in HBM
-        self.inputs = [] if resident else [torch.empty(n_in, dtype=torch.complex64, device=dev)
-                                            for _ in range(self.n_slots)]
+        # memory), unless every sensor's cube is already resident in HBM or the
+        # plan copies it into its own budget
+        self.inputs = [] if resident or self.by_bytes else [
+            torch.empty(n_in, dtype=torch.complex64, device=dev) for _ in range(self.n_slots)]
         self.images = [torch.empty((plan_cfg.n_pix_max, 2), dtype=torch.float32, device=dev)
                        for _ in range(self.n_slots)] if keep_images else None
         self.free = list(range(self.n_slots))
@@ -79,22 +89,26 @@ class Server:
         self.torch.cuda.synchronize()
         self.plan.close()
 
-    def submit(self, items):
-        """items: list of (frame_id, SensorStream, arrival_time); all admitted
-        at once (the caller guarantees len(items) <= free slots)."""
+    def submit(self, items) -> bool:
+        """items: list of (frame_id, SensorStream, arrival_time), at most as many
+        as free slots.  Admits all of them at once and returns True, or (a
+        budget plan without room for them) none and returns False."""
         torch = self.torch
         if not items:
-            return
+            return True
         stream = self.streams[self.next_stream]
-        self.next_stream = (self.next_stream + 1) % len(self.streams)
-        descs = []
+        descs, taken = [], []
         now = time.perf_counter()
         with torch.cuda.stream(stream):
             for fid, sens, arrival in items:
                 slot = self.free.pop()
+                taken.append(slot)
                 fr = sens.frame
+                host = None
                 if self.resident:
                     dst = sens.raw_dev
+                elif self.by_bytes:
+                    dst, host = None, sens.raw_pinned
                 else:
                     dst = self.inputs[slot][:fr.raw.size]
                     dst.copy_(sens.raw_pinned.reshape(-1), non_blocking=True)
@@ -103,9 +117,14 @@ class Server:
                     fid, data=dst, q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel, pixels=sens.pix_dev,
                     n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
                     n_samples=fr.cfg.n_samples, image_out=img, sensor_id=sens.sensor_id,
-                    height=fr.cfg.height))
-                self.inflight[fid] = (slot, sens.sensor_id, arrival, now)
-        self.plan.process(descs, stream)
+                    height=fr.cfg.height, data_host=host))
+        if self.plan.try_process(descs, stream) != _rc.RC_OK:
+            self.free.extend(reversed(taken))
+            return False
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        for (fid, sens, arrival), slot in zip(items, taken):
+            self.inflight[fid] = (slot, sens.sensor_id, arrival, now)
+        return True
 
     def _complete(self, fid: int) -> None:
         slot, sid, arrival, admitted = self.inflight.pop(fid)
@@ -160,8 +179,15 @@ def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, dur
             i += 1
         server.harvest()
         if queue and server.free:
+            # the largest leading part of the queue that fits (a budget plan
+            # admits by bytes: halve the batch until it fits, or wait)
             k = min(len(queue), len(server.free), max_batch)
-            server.submit([queue.popleft() for _ in range(k)])
+            while k and not server.submit([queue[j] for j in range(k)]):
+                k //= 2
+            for _ in range(k):
+                queue.popleft()
+            if not k:
+                server.harvest_until(max(0, len(server.inflight) - 1))
         elif not queue and i < len(arrivals) and not server.inflight:
             time.sleep(max(0.0, min(arrivals[i] - (time.perf_counter() - t0), 1e-3)))
     wall = time.perf_counter() - t0

@@ -278,3 +278,51 @@ def test_static_entry_point_refuses_before_any_device_call(rc):
     d = small.desc()
     st = rc.lib.rc_process_frame_static(C.byref(d), C.byref(fr), det.ctypes.data, 4, cnt.ctypes.data, None)
     assert st == rc.RC_EINVAL and "recheck" in rc.last_error()
+
+
+def _small_frame_desc(rc, n_chirps=16, n_ch=4, n_s=128, n_bins=100, rows=40, cols=50, image=True, host=False):
+    q = np.zeros((n_chirps, n_ch, 2), np.float32)
+    q[..., 0] = np.arange(n_ch) * 0.002
+    vel = np.tile(np.array([[2.0, 0.0]], np.float32), (n_chirps, 1))
+    dummy = np.zeros(16, np.float32)
+    fr = rc.Plan.make_frame(1, data=None if host else dummy, q_tx=q, q_rx=q.copy(), vel=vel, pixels=dummy,
+                            n_rows=rows, n_cols=cols, n_bins=n_bins, n_fft=2 * n_s,
+                            fs=n_s / synth.RADAR["t_chirp"], n_samples=n_s, image_out=dummy if image else None,
+                            data_host=dummy if host else None)
+    return fr, (q, vel, dummy)
+
+
+def test_frame_bytes_follow_the_frames_own_sizes(rc):
+    """RC_MEMORY_BUDGET admits a frame by the device bytes its own sizes need:
+    the interpolation table (16 B per chirp, channel and bin) and per-pixel
+    buffers grow with the frame, a plan's image buffer is counted only without
+    image_out, the input only when it comes from pinned host memory."""
+    cfg = _cfg(rc, hbm_budget_bytes=1 << 30, frame_memory=rc.RC_MEMORY_BUDGET)
+    base, k1 = _small_frame_desc(rc)
+    b0 = rc.frame_bytes(cfg, base)
+    twice, k2 = _small_frame_desc(rc, n_chirps=32)
+    assert rc.frame_bytes(cfg, twice) - b0 >= 16 * 4 * 100 * 16     # 16 more chirps of table
+    no_img, k3 = _small_frame_desc(rc, image=False)
+    assert rc.frame_bytes(cfg, no_img) - b0 >= 40 * 50 * 8            # the image in the arena
+    host, k4 = _small_frame_desc(rc, host=True)
+    assert rc.frame_bytes(cfg, host) - b0 >= 16 * 4 * 128 * 8         # the input cube
+    # far below a slot sized for the plan's limits (128 chirps x 4 x 256 bins, 65536 px)
+    assert b0 < rc.slot_bytes(_cfg(rc)) / 4
+
+
+def test_budget_mode_refusals(rc):
+    """The arena is the budget: a budget plan without a budget, host input
+    outside budget mode, host input next to a device pointer, and a budget
+    smaller than the plan's fixed needs are refused before any device call."""
+    with pytest.raises(rc.RcError) as ei:
+        rc.slot_bytes(_cfg(rc, frame_memory=rc.RC_MEMORY_BUDGET))
+    assert ei.value.status == rc.RC_EINVAL and "hbm_budget_bytes" in rc.last_error()
+    host, keep = _small_frame_desc(rc, host=True)
+    assert rc.validate_frame(_cfg(rc), host) == rc.RC_EINVAL and "data_host" in rc.last_error()
+    both, keep2 = _small_frame_desc(rc, host=True)
+    both.data = keep2[2].ctypes.data
+    assert rc.validate_frame(_cfg(rc, hbm_budget_bytes=1 << 30, frame_memory=rc.RC_MEMORY_BUDGET),
+                             both) == rc.RC_EINVAL
+    with pytest.raises(rc.RcError) as ei:   # the recheck's twiddles alone exceed 4 kB
+        rc.Plan(_cfg(rc, hbm_budget_bytes=4096, frame_memory=rc.RC_MEMORY_BUDGET, max_rechecks=8))
+    assert ei.value.status == rc.RC_ENOMEM

@@ -54,8 +54,9 @@ def test_poisson_serving_results_equal_alone(rc, torch):
     orig_submit = srv.submit
 
     def submit(items):
-        orig_submit(items)
+        ok = orig_submit(items)
         peak[0] = max(peak[0], len(srv.inflight))
+        return ok
 
     srv.submit = submit
     try:
