@@ -799,6 +799,11 @@ def progress(msg: str) -> None:
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+#: precision forms by name (constants of the binding)
+FORMS = {"fp32": "RC_PREC_FP32", "fp32-split": "RC_PREC_FP32_SPLIT", "fp16-spectrum": "RC_PREC_FP16",
+         "bf16-spectrum": "RC_PREC_BF16"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -817,6 +822,9 @@ def main(argv=None):
                     help="only the mixed-size batch run (printed as its own JSON line)")
     ap.add_argument("--sliding-only", action="store_true",
                     help="only the continuous-SAR run (printed as its own JSON line)")
+    ap.add_argument("--form-only", choices=tuple(FORMS), default=None,
+                    help="only the main frame in one precision form, one frame in flight (printed as its own "
+                         "JSON line; for profiling that form's kernels)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for HBM counter calibration)")
@@ -847,6 +855,16 @@ def main(argv=None):
     if args.batched_only:
         sensors = make_sensors(rc, synth, torch, 32)
         print(json.dumps({"batched_mixed": batched_mixed_median(rc, synth, torch, sensors)}), flush=True)
+        return 0
+    if args.form_only:
+        prec = getattr(rc, FORMS[args.form_only])
+        frame = synth.make_frame(synth.CONFIGS[args.workload], device="cuda")
+        one = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols, prec, args.steps,
+                            args.warmup, depth=1)
+        st = one["stages"].mean(axis=0)
+        print(json.dumps({"form": args.form_only, "workload": args.workload, "frames": args.steps,
+                          "stages_ms": dict(zip(("range", "tables", "backprojection", "detection"),
+                                                map(float, st)))}), flush=True)
         return 0
     if args.sliding_only:
         drive = make_drive(synth, torch)

@@ -82,22 +82,25 @@ struct Leg {
   float dop;  // exact only: Doppler index shift of the leg
 };
 
-// Per-pixel constants of the split form's series: h = 1 / (2R), k = 1 / R^2.
+// Per-pixel coefficients of the split form's series in N (below).
 struct PixAux {
-  float h, k;
+  float c[5];
 };
 
 // Split-phase offset by series.  With u = N / R^2,
 //   delta = sqrt(R^2 + N) - R = (N / (2R)) (1 + u G(u)),
 //   G(u) = -1/4 + u/8 - 5u^2/64 + 7u^3/128 - ...
-// (the binomial series of sqrt(1 + u)).  G is evaluated as the cubic that
+// (the binomial series of sqrt(1 + u)).  G is taken as the cubic that
 // interpolates it at the four Chebyshev nodes of [-kSeriesU, kSeriesU]
 // (kSeriesU = 0.1): with the coefficients rounded to float, 1 + u G(u) is off
-// by at most 5.7e-8 of itself there (the Taylor cubic: 4.5e-7).  Far from the
-// aperture (R above ~20 times the antennas' spread) delta then costs five
-// FMA-class instructions and four multiplies instead of a square root and a
-// reciprocal, both quarter-rate; waves with any pixel closer take the exact
-// form.
+// by at most 5.7e-8 of itself there (the Taylor cubic: 4.5e-7).  Multiplied
+// out, delta is a quintic in N with no constant term whose coefficients
+// depend on the pixel only: c1 = 1/(2R), c(i+2) = G_i / (2R^(2i+3)), so a leg
+// costs four FMAs and a multiply (Horner in N) once per pixel has formed the
+// five; its rounding matches the nested form's (2.0e-7 of delta at most, over
+// R in [0.5, 60] and the whole u range).  Far from the aperture (R above ~20
+// times the antennas' spread) this replaces a square root and a reciprocal,
+// both quarter-rate; waves with any pixel closer take the exact form.
 constexpr float kSeriesU = 0.1f;
 constexpr float kG0 = -0.24999947845935822f, kG1 = 0.12499959766864777f, kG2 = -0.0785374641418457f,
                 kG3 = 0.05501168593764305f;
@@ -118,12 +121,11 @@ __device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p, const P
   } else if constexpr (FORM == kBpSplit) {
     const float n = fmaf(q.x, p.x, fmaf(q.y, p.y, q.z));
     if constexpr (SERIES) {
-      const float u = n * x_.k;
-      const float w = n * x_.h;
-      float g = fmaf(kG3, u, kG2);
-      g = fmaf(g, u, kG1);
-      g = fmaf(g, u, kG0);
-      l.d = fmaf(w * u, g, w);
+      float t = fmaf(x_.c[4], n, x_.c[3]);
+      t = fmaf(t, n, x_.c[2]);
+      t = fmaf(t, n, x_.c[1]);
+      t = fmaf(t, n, x_.c[0]);
+      l.d = t * n;
     } else {
       l.d = n * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(p.z, p.z, n)) + p.z);
     }
@@ -167,12 +169,17 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
   // path, less a1 frac(2R): the split form's TX leg carries the reference
   // phase frac(2R), so a term's phase and index both come from one sum
   const float fb = FORM == kBpSplit ? fmaf(-a.a1, p.w, fidx) : fidx;
-  // split form's series: 1 / (2R) and 1 / R^2 (p.z = R)
-  PixAux aux{0.f, 0.f};
+  // split form's series coefficients from 1 / (2R) and 1 / R^2 (p.z = R)
+  PixAux aux{};
   if constexpr (FORM == kBpSplit && SERIES) {
     const float ir = __builtin_amdgcn_rcpf(p.z);
-    aux.h = 0.5f * ir;
-    aux.k = ir * ir;
+    const float h = 0.5f * ir, k = ir * ir;
+    const float hk = h * k, hk2 = hk * k, hk3 = hk2 * k;
+    aux.c[0] = h;
+    aux.c[1] = hk * kG0;
+    aux.c[2] = hk2 * kG1;
+    aux.c[3] = hk3 * kG2;
+    aux.c[4] = (hk3 * k) * kG3;
   }
   float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
   // SUMS == 3: the plain, cos- and sin-weighted sums over the chirps done,
