@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import contextlib
+import dataclasses
 import gc
 import json
 import os
@@ -719,10 +720,16 @@ def batched_mixed_median(rc, synth, torch, sensors, repeats=3, **kw):
     med["resident"] = {"frames_per_s": res[len(res) // 2]["frames_per_s"],
                        "frames_per_s_runs": [r["frames_per_s"] for r in res],
                        "bp_terms_per_s_incl_all_stages": res[len(res) // 2]["bp_terms_per_s_incl_all_stages"]}
+    # the paper's plain single-precision form on the same resident batches
+    res = sorted((batched_mixed(rc, synth, torch, sensors, resident=True, precision="fp32", **kw)
+                  for _ in range(repeats)), key=lambda r: r["frames_per_s"])
+    med["resident_fp32"] = {"frames_per_s": res[len(res) // 2]["frames_per_s"],
+                            "frames_per_s_runs": [r["frames_per_s"] for r in res],
+                            "bp_terms_per_s_incl_all_stages": res[len(res) // 2]["bp_terms_per_s_incl_all_stages"]}
     return med
 
 
-def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=False):
+def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=False, precision="fp32-split"):
     """Frames of mixed sizes in batches of `batch` frames per rc_process_batch
     (one back-projection launch per TX-group width and 16 frames), each batch
     including the pinned-memory upload of its beat cubes (resident=False) or
@@ -731,7 +738,8 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=F
     the GPU processes the current one."""
     from paper_2306_09784_amd import serve
 
-    srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch), n_streams=2, resident=resident)
+    srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch, precision=getattr(rc, FORMS[precision])),
+                       n_streams=2, resident=resident)
     try:
         order = [sensors[i % len(sensors)] for i in range(n_frames)]
         with no_gc():
@@ -753,7 +761,7 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=F
     finally:
         srv.close()
     terms = sum(s.frame.n_rows * s.frame.n_cols * s.frame.cfg.n_chirps * s.frame.cfg.n_channels for s in order)
-    out = {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "precision": "fp32-split",
+    out = {"frames": n_frames, "batch": batch, "batches_in_flight": 2, "precision": precision,
            "frames_per_s": n_frames / wall,
            "bp_terms_per_s_incl_all_stages": terms / wall, "wall_s": wall, "inputs": (
                "beat cubes resident in HBM" if resident else "beat cubes uploaded from pinned host memory")}
@@ -780,6 +788,37 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
     res["load"] = load
     res["precision"] = "fp32-split"
     res["realtime_bound_ms"] = 1024 * synth.RADAR["t_pri"] * 1e3
+    return res
+
+
+def serving_budget(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=64, max_batch=32):
+    """serving() with admission by bytes: one HBM arena sized for two batches
+    of the sensors' mean frame (each frame's cube copied from pinned memory
+    into it by the plan), against the slots of the plan's limits plus a device
+    input buffer per slot that the slot plan needs for the same run."""
+    from paper_2306_09784_amd import serve
+
+    base = mixed_plan_config(rc, synth, sensors, slots)
+    probe = dataclasses.replace(base, frame_memory=rc.RC_MEMORY_BUDGET, hbm_budget_bytes=1 << 40)
+    sizes = []
+    for sn in sensors:
+        fr = sn.frame
+        sizes.append(rc.frame_bytes(probe, rc.Plan.make_frame(
+            0, data=None, data_host=sn.raw_pinned, q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel, pixels=sn.pix_dev,
+            n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
+            n_samples=fr.cfg.n_samples)))
+    budget = int(max(2 * max(sizes), 2 * max_batch * float(np.mean(sizes))))
+    n_in = base.n_chirps_max * base.n_channels_max * base.n_samples_max
+    slot_mode = rc.slot_bytes(base) * slots + slots * n_in * 8
+    srv = serve.Server(dataclasses.replace(probe, hbm_budget_bytes=budget), n_streams=2)
+    try:
+        with no_gc():
+            res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s,
+                                    max_batch=max_batch)
+    finally:
+        srv.close()
+    res.update(load=load, precision="fp32-split", hbm_budget_bytes=budget, slot_mode_hbm_bytes=slot_mode,
+               frame_bytes_min=min(sizes), frame_bytes_max=max(sizes), frame_bytes_mean=float(np.mean(sizes)))
     return res
 
 
@@ -1028,6 +1067,9 @@ def main(argv=None):
             out["serving"] = serving(rc, synth, torch, sensors, out["batched_mixed"]["frames_per_s"],
                                      args.serve_seconds)
             progress("serving done")
+            out["serving"]["by_bytes"] = serving_budget(rc, synth, torch, sensors,
+                                                        out["batched_mixed"]["frames_per_s"], args.serve_seconds / 3)
+            progress("serving by bytes done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_budget)
         if forms_out:
