@@ -158,3 +158,33 @@ def detection_mismatch(gpu_dets, oracle_cfar, power, amp_err, n_cols, guard, tra
         if not fragile[r - h, c - h]:
             bad.append((cell, float(power[r, c]), float(thr[r - h, c - h])))
     return bad, len(diff), int(fragile.sum())
+
+
+def band_mismatch(gpu_dets, power, n_cols, guard, train, pfa, margin):
+    """Cells on which the GPU's detection list and the oracle's CA-CFAR on the
+    oracle's power image disagree farther than `margin` (relative) from the
+    oracle's threshold: the detection contract's violations.  Returns (those
+    cells, number of disagreeing cells)."""
+    h = guard + train
+    n_train = (2 * h + 1) ** 2 - (2 * guard + 1) ** 2
+    alpha = O.cfar_alpha(n_train, pfa)
+    R, C = power.shape
+    view = np.lib.stride_tricks.sliding_window_view
+    outer = view(power, (2 * h + 1, 2 * h + 1)).sum(axis=(-1, -2))
+    inner = view(power, (2 * guard + 1, 2 * guard + 1)).sum(axis=(-1, -2))
+    off = h - guard
+    thr = alpha * (outer - inner[off:off + R - 2 * h, off:off + C - 2 * h]) / n_train
+    cell_p = power[h:R - h, h:C - h]
+    det_o = np.zeros((R, C), bool)
+    det_o[h:R - h, h:C - h] = cell_p > thr
+    det_g = np.zeros(R * C, bool)
+    det_g[gpu_dets["pixel"].astype(np.int64)] = True
+    det_g = det_g.reshape(R, C)
+    diff = np.argwhere(det_g != det_o)
+    bad = []
+    for r, c in diff:
+        inside = h <= r < R - h and h <= c < C - h
+        if not inside or abs(power[r, c] - thr[r - h, c - h]) > margin * thr[r - h, c - h]:
+            bad.append(int(r * n_cols + c))
+    return bad, len(diff)
+

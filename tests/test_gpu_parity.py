@@ -36,6 +36,7 @@ PLAIN_TOL = 5e-3
 SPLIT_TOL = 2e-4
 BP_FLOOR = 1e-5
 PLAIN, SPLIT = 0, 1
+MARGIN = 3e-2    # the plan's CFAR band (relative to the threshold) in the end-to-end cases
 R = synth.RADAR
 PRECISIONS = [pytest.param(PLAIN, id="fp32"), pytest.param(SPLIT, id="split")]
 
@@ -322,7 +323,7 @@ def test_bp_parity_small_lattices(rc, torch, n_rows, n_cols):
 def test_end_to_end_plain_small(rc, torch, precision):
     """256 samples x 128 chirps x 4 RX on a 256 x 256 grid: image and detections."""
     fr = SC.small_frame()
-    with rc.Plan(SC.plan_config(rc, [fr], precision=precision)) as plan:
+    with rc.Plan(SC.plan_config(rc, [fr], precision=precision, cfar_margin_rel=MARGIN)) as plan:
         out = SC.run_gpu(rc, plan, fr, torch)
     ora = SC.run_oracle(fr)
     bound = _check_image("end_to_end_small", fr, out["image"], ora, precision)
@@ -334,6 +335,13 @@ def test_end_to_end_plain_small(rc, torch, precision):
             n_oracle=len(ora["cfar"][0]), n_diff=n_diff, n_fragile=n_fragile, n_robust_mismatch=len(bad))
     assert not bad, bad[:5]
     assert len(dets) > 0
+    if precision == SPLIT:
+        # the detection contract: the lists differ only within the plan's band
+        # of the oracle's threshold, where the GPU flags its own detections
+        out_band, n_d = SC.band_mismatch(dets, ora["power"], fr.n_cols, 2, 8, 1e-4, MARGIN)
+        assert not out_band, out_band[:5]
+        g_rel = np.abs(dets["power"].astype(np.float64) - dets["threshold"]) / dets["threshold"]
+        assert np.array_equal((dets["flags"] & rc.RC_DET_NEAR_THRESHOLD) != 0, g_rel <= MARGIN)
     # reported power / threshold match the oracle's at common cells
     common, gi, oi = np.intersect1d(dets["pixel"], ora["cfar"][0], return_indices=True)
     pw_err = 2 * np.sqrt(ora["cfar"][1][oi]) * amp_err.reshape(-1)[common] + amp_err.reshape(-1)[common] ** 2
