@@ -791,6 +791,18 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
     return res
 
 
+def serving_legs(rc, synth, torch, sensors, capacity_fps, seconds):
+    """Poisson serving at 70 % of the uploaded batch capacity (half the time),
+    at 50 % (a quarter), and at 70 % with admission by bytes (a quarter)."""
+    res = serving(rc, synth, torch, sensors, capacity_fps, seconds / 2)
+    progress("serving done")
+    res["at_half_load"] = serving(rc, synth, torch, sensors, capacity_fps, seconds / 4, load=0.5)
+    progress("serving at half load done")
+    res["by_bytes"] = serving_budget(rc, synth, torch, sensors, capacity_fps, seconds / 4)
+    progress("serving by bytes done")
+    return res
+
+
 def serving_budget(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=64, max_batch=32):
     """serving() with admission by bytes: one HBM arena sized for two batches
     of the sensors' mean frame (each frame's cube copied from pinned memory
@@ -859,6 +871,9 @@ def main(argv=None):
                     help="skip the split-phase, paper-configuration, batched and serving runs")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the mixed-size batch run (printed as its own JSON line)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the mixed-size batch capacity (uploaded inputs, one run) and the serving runs "
+                         "(printed as their own JSON line)")
     ap.add_argument("--sliding-only", action="store_true",
                     help="only the continuous-SAR run (printed as its own JSON line)")
     ap.add_argument("--form-only", choices=tuple(FORMS), default=None,
@@ -894,6 +909,12 @@ def main(argv=None):
     if args.batched_only:
         sensors = make_sensors(rc, synth, torch, 32)
         print(json.dumps({"batched_mixed": batched_mixed_median(rc, synth, torch, sensors)}), flush=True)
+        return 0
+    if args.serving_only:
+        sensors = make_sensors(rc, synth, torch, 32)
+        cap = batched_mixed(rc, synth, torch, sensors)
+        print(json.dumps({"batched_mixed": cap, "serving": serving_legs(
+            rc, synth, torch, sensors, cap["frames_per_s"], args.serve_seconds)}), flush=True)
         return 0
     if args.form_only:
         prec = getattr(rc, FORMS[args.form_only])
@@ -1064,12 +1085,8 @@ def main(argv=None):
         out["batched_mixed"] = batched_mixed_median(rc, synth, torch, sensors)
         progress(f"batched mixed: {out['batched_mixed']['frames_per_s']:.0f} frames/s")
         if args.serve_seconds > 0:
-            out["serving"] = serving(rc, synth, torch, sensors, out["batched_mixed"]["frames_per_s"],
-                                     args.serve_seconds)
-            progress("serving done")
-            out["serving"]["by_bytes"] = serving_budget(rc, synth, torch, sensors,
-                                                        out["batched_mixed"]["frames_per_s"], args.serve_seconds / 3)
-            progress("serving by bytes done")
+            out["serving"] = serving_legs(rc, synth, torch, sensors, out["batched_mixed"]["frames_per_s"],
+                                          args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_budget)
         if forms_out:

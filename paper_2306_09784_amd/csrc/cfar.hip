@@ -96,8 +96,12 @@ __global__ __launch_bounds__(kThreads) void cfar_kernel(CfarMulti m) {
   }
 }
 
-constexpr int kCompactThreads = 1024;
 constexpr int kCompactWords = 8;  // mask words per thread per sweep
+// A frame whose mask fits in this many sweeps of a 256-thread workgroup is
+// compacted by one: while another stream's back-projection holds the CUs, a
+// workgroup of four waves finds room as soon as one of its workgroups ends,
+// where one of sixteen waves may wait for a CU to drain.
+constexpr int kCompactSmallSweeps = 4;
 
 // Inclusive prefix sum over the 64 lanes of a wave (shuffles, no barrier).
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
@@ -111,22 +115,23 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
 }
 
 // Ordered compaction of one frame's detection mask: each sweep covers
-// 1024 x 8 consecutive mask words; a thread counts its eight words, the
-// workgroup scans the thread totals (wave scans, then a scan of the 16 wave
+// THREADS x 8 consecutive mask words; a thread counts its eight words, the
+// workgroup scans the thread totals (wave scans, then a scan of the wave
 // totals), every thread writes the cell index of each set bit of its words
 // to its output slot, and then all threads copy the sweep's records from
 // those cells in parallel (detections cluster, so a thread may own many set
 // bits: copying them one by one would chain that many memory latencies).
 // Output order is ascending pixel index.
-__global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m) {
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void compact_kernel(CompactMulti m) {
   const CompactArgs a = m.f[__builtin_amdgcn_readfirstlane((int)blockIdx.x)];  // one workgroup per frame
-  __shared__ int wave_sum[kCompactThreads / 64];
+  __shared__ int wave_sum[THREADS / 64];
   __shared__ int64_t base_sh;
   const int64_t n_words = (int64_t)a.n_rows * a.words_per_row;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) base_sh = 0;
   __syncthreads();
-  for (int64_t w0 = 0; w0 < n_words; w0 += (int64_t)kCompactThreads * kCompactWords) {
+  for (int64_t w0 = 0; w0 < n_words; w0 += (int64_t)THREADS * kCompactWords) {
     const int64_t wt = w0 + (int64_t)threadIdx.x * kCompactWords;
     unsigned long long word[kCompactWords];
     int total = 0;
@@ -139,9 +144,9 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m
     if (lane == 63) wave_sum[wave] = incl;
     __syncthreads();
     if (wave == 0) {
-      const int ws = lane < kCompactThreads / 64 ? wave_sum[lane] : 0;
+      const int ws = lane < THREADS / 64 ? wave_sum[lane] : 0;
       const int wincl = wave_inclusive_scan(ws);
-      if (lane < kCompactThreads / 64) wave_sum[lane] = wincl - ws;  // exclusive
+      if (lane < THREADS / 64) wave_sum[lane] = wincl - ws;  // exclusive
     }
     __syncthreads();
     const int64_t base = base_sh;
@@ -163,11 +168,11 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactMulti m
       }
     }
     __syncthreads();
-    if (threadIdx.x == kCompactThreads - 1) base_sh = pos;  // the last thread ends the sweep
+    if (threadIdx.x == THREADS - 1) base_sh = pos;  // the last thread ends the sweep
     __syncthreads();
     const int64_t end = base_sh < a.cap ? base_sh : a.cap;
     const int64_t hend = base_sh < a.host_cap ? base_sh : a.host_cap;
-    for (int64_t i = base + threadIdx.x; i < end; i += kCompactThreads) {
+    for (int64_t i = base + threadIdx.x; i < end; i += THREADS) {
       const rc_detection d = a.det_cell[a.det_out[i].pixel];
       a.det_out[i] = d;
       if (i < hend) a.host_out[i] = d;
@@ -210,7 +215,13 @@ hipError_t launch_compact(const CompactMulti& m, hipStream_t s) {
         a.host_cap < 0 || a.host_cap > a.cap || (a.host_cap > 0 && !a.host_out))
       return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)m.n_frames), dim3(kCompactThreads), 0, s, m);
+  int64_t words = 0;
+  for (int i = 0; i < m.n_frames; ++i)
+    words = std::max<int64_t>(words, (int64_t)m.f[i].n_rows * m.f[i].words_per_row);
+  if (words <= (int64_t)kCompactSmallSweeps * 256 * kCompactWords)
+    hipLaunchKernelGGL(compact_kernel<256>, dim3((unsigned)m.n_frames), dim3(256), 0, s, m);
+  else
+    hipLaunchKernelGGL(compact_kernel<1024>, dim3((unsigned)m.n_frames), dim3(1024), 0, s, m);
   return hipGetLastError();
 }
 

@@ -175,6 +175,11 @@ struct Plan {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   std::map<size_t, size_t> free_list;
+  // inputs handed over in pinned host memory are copied on a stream of their
+  // own (default priority), so that a batch's copies overlap the kernels of
+  // the batches before it; the batch's stream waits for them by an event
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t copied = nullptr;
 };
 
 // First fit from the arena; returns the offset or SIZE_MAX when no free range holds len.
@@ -414,7 +419,10 @@ void free_slot(Slot& s, bool owns_device) {
 void free_plan(Plan* p) {
   if (!p) return;
   for (Slot& s : p->slots) free_slot(s, !p->arena);
+  if (p->copy_stream) (void)hipStreamSynchronize(p->copy_stream);
   if (p->arena) (void)hipFree(p->arena);
+  if (p->copied) (void)hipEventDestroy(p->copied);
+  if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   for (Sensor& s : p->sensors)
     if (s.done) (void)hipEventDestroy(s.done);
   if (p->ring) (void)hipFree(p->ring);
@@ -1161,6 +1169,12 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
       return fail(RC_ENOMEM, "device arena of %zu bytes: %s", p->arena_bytes, hipGetErrorString(e));
     }
     p->free_list.emplace(0, p->arena_bytes);
+    e = hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->copied, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(RC_EHIP, "copy stream: %s", hipGetErrorString(e));
+    }
   }
   for (Slot& s : p->slots) {
     if (!budget_mode) {
@@ -1295,6 +1309,7 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   }
   auto undo = [&](rc_status r) {  // a failed batch leaves no slot busy and no stream advanced
     (void)hipStreamSynchronize(st);
+    if (p->copy_stream) (void)hipStreamSynchronize(p->copy_stream);  // no copy still writes a freed range
     for (Slot* q : slot)
       if (q) { q->busy = false; q->frame_id = -1; q->sensor = -1; q->arena_len = 0; q->input = nullptr; }
     for (const auto& t : taken) arena_free(p, t.first, t.second);
@@ -1325,10 +1340,21 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
     if (r != RC_OK) return undo(r);
   }
   // inputs handed over in pinned host memory: copied into the frames' arena
-  // shares ahead of their kernels (the paper's pinned Load)
+  // shares on the plan's copy stream (the paper's pinned Load), which the
+  // batch's stream waits for before its kernels.  A share is taken only from
+  // ranges whose frames have completed, so no earlier work on any stream
+  // still reads it.
+  bool any_host = false;
   for (int i = 0; i < n_frames; ++i)
-    if (frames[i].data_host)
-      RC_BATCH(hipMemcpyAsync(slot[i]->input, frames[i].data_host, fsz[i].input, hipMemcpyHostToDevice, st));
+    if (frames[i].data_host) {
+      RC_BATCH(hipMemcpyAsync(slot[i]->input, frames[i].data_host, fsz[i].input, hipMemcpyHostToDevice,
+                              p->copy_stream));
+      any_host = true;
+    }
+  if (any_host) {
+    RC_BATCH(hipEventRecord(p->copied, p->copy_stream));
+    RC_BATCH(hipStreamWaitEvent(st, p->copied, 0));
+  }
   // 0: every frame's geometry from its staging buffer, one launch per 32 frames
   for (int i0 = 0; i0 < n_frames; i0 += rc::UploadMulti::kMax) {
     rc::UploadMulti m;

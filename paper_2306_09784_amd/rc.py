@@ -391,7 +391,7 @@ class Plan:
     def detections(self, frame_id: int, cap: Optional[int] = None) -> np.ndarray:
         if cap is None:
             cap = self.cfg.max_detections
-        buf = np.zeros(cap, dtype=DETECTION_DTYPE)
+        buf = np.empty(cap, dtype=DETECTION_DTYPE)   # the first n records are written
         n = C.c_int64()
         st = lib.rc_detections(self.handle, frame_id,
                                buf.ctypes.data_as(C.POINTER(rc_detection)), cap, C.byref(n))

@@ -80,8 +80,15 @@ class Server:
                        for _ in range(self.n_slots)] if keep_images else None
         self.free = list(range(self.n_slots))
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        # the cubes' host-to-device copies run on a stream of their own: a
+        # batch's kernels wait for its copies by an event, and the copies of
+        # the next batch proceed while the current one computes
+        self.copy_stream = torch.cuda.Stream()
         self.next_stream = 0
         self.inflight: Dict[int, tuple] = {}   # frame_id -> (slot, sensor_id, arrival, admitted)
+        # per stream, the frame ids of its batches in submission order: a
+        # stream's batches complete in that order, and a batch's frames together
+        self.pending = [collections.deque() for _ in range(n_streams)]
         self.results: List[Completed] = []
         self.image_of: Dict[int, np.ndarray] = {}
 
@@ -99,6 +106,7 @@ class Server:
         stream = self.streams[self.next_stream]
         descs, taken = [], []
         now = time.perf_counter()
+        copied = False
         with torch.cuda.stream(stream):
             for fid, sens, arrival in items:
                 slot = self.free.pop()
@@ -110,17 +118,25 @@ class Server:
                 elif self.by_bytes:
                     dst, host = None, sens.raw_pinned
                 else:
+                    # a free slot's buffer is no longer read by its last frame
                     dst = self.inputs[slot][:fr.raw.size]
-                    dst.copy_(sens.raw_pinned.reshape(-1), non_blocking=True)
+                    with torch.cuda.stream(self.copy_stream):
+                        dst.copy_(sens.raw_pinned.reshape(-1), non_blocking=True)
+                    copied = True
                 img = self.images[slot] if self.images is not None else None
                 descs.append(_rc.Plan.make_frame(
                     fid, data=dst, q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel, pixels=sens.pix_dev,
                     n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs,
                     n_samples=fr.cfg.n_samples, image_out=img, sensor_id=sens.sensor_id,
                     height=fr.cfg.height, data_host=host))
+        if copied:
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+            stream.wait_event(ev)
         if self.plan.try_process(descs, stream) != _rc.RC_OK:
             self.free.extend(reversed(taken))
             return False
+        self.pending[self.next_stream].append([fid for fid, _, _ in items])
         self.next_stream = (self.next_stream + 1) % len(self.streams)
         for (fid, sens, arrival), slot in zip(items, taken):
             self.inflight[fid] = (slot, sens.sensor_id, arrival, now)
@@ -138,13 +154,19 @@ class Server:
         self.results.append(Completed(fid, sid, arrival, admitted, done, dets))
 
     def harvest(self, block: bool = False) -> int:
-        """Collects every completed frame (all in flight if block); returns how many."""
+        """Collects every completed frame (all in flight if block); returns how
+        many.  Polls only the oldest batch of each stream: the later ones of a
+        stream cannot have completed before it."""
         n = 0
-        for fid in list(self.inflight):
-            if not block and not self.plan.poll(fid):
-                continue
-            self._complete(fid)
-            n += 1
+        for q in self.pending:
+            while q:
+                batch = [f for f in q[0] if f in self.inflight]
+                if batch and not block and not self.plan.poll(batch[-1]):
+                    break
+                q.popleft()
+                for fid in batch:
+                    self._complete(fid)
+                n += len(batch)
         return n
 
     def harvest_until(self, max_inflight: int) -> int:
@@ -157,9 +179,15 @@ class Server:
 
 
 def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, duration_s: float,
-                seed: int = 4000, max_batch: Optional[int] = None) -> dict:
+                seed: int = 4000, max_batch: Optional[int] = None, max_wait_s: float = 2e-3,
+                poll_s: float = 1e-4) -> dict:
     """Open-loop Poisson arrivals at rate_hz (sensors chosen uniformly) for
-    duration_s; returns throughput and latency statistics."""
+    duration_s; returns throughput and latency statistics.  Waiting frames are
+    admitted as a batch when a full batch (max_batch) is waiting, when no batch
+    is in flight, or when fewer batches than streams are in flight and the
+    oldest has waited max_wait_s: under load the batches grow with the frames
+    that arrive while others run (a batch's fixed costs are paid per batch),
+    when idle a frame goes at once."""
     rng = np.random.default_rng(seed)
     n_expected = int(rate_hz * duration_s * 1.2) + 16
     gaps = rng.exponential(1.0 / rate_hz, n_expected)
@@ -167,6 +195,7 @@ def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, dur
     arrivals = arrivals[arrivals < duration_s]
     who = rng.integers(0, len(sensors), len(arrivals))
     queue = collections.deque()
+    sizes = []   # frames per admitted batch
     t0 = time.perf_counter()
     i = 0
     fid = 1
@@ -178,7 +207,10 @@ def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, dur
             fid += 1
             i += 1
         server.harvest()
-        if queue and server.free:
+        in_flight = sum(len(q) for q in server.pending)
+        ready = queue and (len(queue) >= max_batch or not server.inflight or
+                           (in_flight < len(server.streams) and now - (queue[0][2] - t0) >= max_wait_s))
+        if ready and server.free:
             # the largest leading part of the queue that fits (a budget plan
             # admits by bytes: halve the batch until it fits, or wait)
             k = min(len(queue), len(server.free), max_batch)
@@ -186,10 +218,14 @@ def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, dur
                 k //= 2
             for _ in range(k):
                 queue.popleft()
-            if not k:
+            if k:
+                sizes.append(k)
+            else:
                 server.harvest_until(max(0, len(server.inflight) - 1))
         elif not queue and i < len(arrivals) and not server.inflight:
             time.sleep(max(0.0, min(arrivals[i] - (time.perf_counter() - t0), 1e-3)))
+        elif server.inflight:
+            time.sleep(poll_s)  # between polls of the GPU, rather than spinning on the runtime
     wall = time.perf_counter() - t0
     lat = np.array([r.done - r.arrival for r in server.results])
     per_sensor = collections.defaultdict(list)
@@ -205,6 +241,8 @@ def run_poisson(server: Server, sensors: List[SensorStream], rate_hz: float, dur
         "max_ms": 1e3 * float(lat.max()) if len(lat) else None,
         "worst_sensor_p99_ms": 1e3 * max(float(np.percentile(v, 99)) for v in per_sensor.values())
         if per_sensor else None,
+        "batches": len(sizes),
+        "mean_batch": float(np.mean(sizes)) if sizes else None,
     }
 
 
