@@ -8,13 +8,16 @@ Tolerances (derivation in the design notes):
     floor, where S(p) is the oracle's sum of term magnitudes, e_phase the
     bound on a term's phase error in turns and gamma the bound on the
     accumulation rounding (terms per accumulator x 2^-24); e_phase is
-    2^-21 d_max / lambda for plain single precision and 2^-19 Q / lambda + 2e-6
-    for the split-phase form (Q: largest antenna offset from the aperture
-    centre);
+    2^-22 d_max / lambda for plain single precision (two ulps of the longest
+    two-way path in wavelengths: the square root's biased rounding and the
+    path's sums each stay within an ulp) and 2^-19 Q / lambda + 2e-6 for the
+    split-phase form (Q: largest antenna offset from the aperture centre);
   * image-level max |dP| / max |P|: PLAIN_TOL (single precision, the paper's
     form: a pixel's mean phase error reaches ~4e-4 turns) and SPLIT_TOL;
   * detections: identical lists except cells whose oracle decision is not
-    robust to the per-pixel image error bound (see sar_cases).
+    robust to the per-pixel image error bound (see sar_cases); for the
+    split-phase form, every disagreement within the plan's band of the
+    oracle's threshold.
 """
 import dataclasses
 import json
@@ -75,7 +78,7 @@ def _phase_bound(frame, precision):
     corners = np.array([[frame.pix[:, 0].min(), frame.pix[:, 1].min()], [frame.pix[:, 0].max(), frame.pix[:, 1].max()],
                         [frame.pix[:, 0].min(), frame.pix[:, 1].max()], [frame.pix[:, 0].max(), frame.pix[:, 1].min()]])
     d_max = 2 * np.sqrt(((corners[:, None, :] - q[None]) ** 2).sum(-1) + frame.cfg.height ** 2).max()
-    return 2.0 ** -21 * d_max / lam + 1e-5
+    return 2.0 ** -22 * d_max / lam + 1e-5
 
 
 def _amp_bound(frame, ora, precision, pix_index=None):

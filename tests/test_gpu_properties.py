@@ -84,7 +84,7 @@ def _bound(fr, spec, pix=None):
     lo, hi = pix.min(0), pix.max(0)
     corners = np.array([[lo[0], lo[1]], [hi[0], hi[1]], [lo[0], hi[1]], [hi[0], lo[1]]])
     d_max = 2 * np.sqrt(((corners[:, None, :] - q[None]) ** 2).sum(-1)).max()
-    e = 2.0 ** -21 * d_max / (R["c"] / R["f0"]) + 1e-5
+    e = 2.0 ** -22 * d_max / (R["c"] / R["f0"]) + 1e-5
     gamma = (fr.cfg.n_chirps * fr.cfg.n_channels / 2 + 2) * 2.0 ** -24
     return (2 * math.pi * e + gamma) * S
 

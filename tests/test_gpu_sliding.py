@@ -135,7 +135,7 @@ def _bound(fr, k, oblocks, b, K, precision, scale):
             lo, hi = pix.min(0), pix.max(0)
             corners = np.array([[lo[0], lo[1]], [hi[0], hi[1]], [lo[0], hi[1]], [hi[0], lo[1]]])
             d_max = 2 * np.sqrt(((corners[:, None, :] - q[None]) ** 2).sum(-1) + h * h).max()
-            e = 2.0 ** -21 * d_max / lam + 1e-5
+            e = 2.0 ** -22 * d_max / lam + 1e-5
         e_phase = max(e_phase, e)
     S = len(oblocks[b]["s"])
     gamma = (S * oblocks[b]["s"].shape[1] + 3 * K + 4) * 2.0 ** -24
