@@ -42,7 +42,7 @@ rc_status fail(rc_status st, const char* fmt, ...) {
   } while (0)
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kDetPrefix = 1024;  // detections copied back asynchronously per frame
+constexpr int kDetPrefix = 1024;  // detections the compaction writes straight into mapped pinned memory per frame
 // longest two-way path, in wavelengths, whose phase the single-precision forms
 // hand to the hardware sine and cosine (their argument reduction is verified
 // to 2^16 turns)

@@ -4,7 +4,8 @@ The runtime is compiled again with the sanitizer on its host part only (the
 device code is unchanged; GPU sanitizers are not used), linked into a
 separate library in a temporary directory, and a C driver calls every entry
 point that needs no GPU: descriptor validation and slot sizing (with the
-recheck and continuous-SAR state on), the grid generators, the argument
+recheck and continuous-SAR state on), a frame's validation and its bytes
+under an HBM-budget plan, the grid generators, the argument
 checks of the batch and resampling calls, and plan creation refused by the
 HBM budget before any device call.  Any out-of-bounds access or leak in those
 paths fails the test."""
@@ -52,6 +53,29 @@ int main(void) {
   CHECK(rc_process_batch(NULL, NULL, 0, NULL) == RC_EINVAL);
   CHECK(rc_resample_polar(NULL, 5, 4, 0, 0, 1, 0.1, 0, 0.1, NULL, -1, NULL, NULL) == RC_EINVAL);
   CHECK(rc_resample_polar(NULL, 5, 4, 0, 0, 1, 0.1, 0, 0.1, NULL, 0, NULL, NULL) == RC_OK);
+  /* a frame checked and sized on the host: the limits, the bytes an HBM-budget
+     plan gives it (more with its cube in pinned host memory), host input
+     refused outside budget mode */
+  float* q = calloc(8 * 4 * 2, sizeof(float));
+  float* vel = calloc(8 * 2, sizeof(float));
+  rc_frame f = {0};
+  f.frame_id = 1; f.n_samples = 64; f.n_fft = 128; f.n_bins = 40; f.n_chirps = 8; f.n_channels = 4;
+  f.fs = 64 / 102.4e-6; f.input_kind = RC_INPUT_RAW; f.data = q; f.q_tx = q; f.q_rx = q; f.vel = vel;
+  f.pixels = q; f.n_rows = 10; f.n_cols = 12;
+  CHECK(rc_frame_validate(&d, &f) == RC_OK);
+  d.frame_memory = RC_MEMORY_BUDGET;
+  d.hbm_budget_bytes = (int64_t)1 << 30;
+  int64_t b_dev = 0, b_host = 0;
+  CHECK(rc_frame_bytes(&d, &f, &b_dev) == RC_OK && b_dev > 0);
+  f.data = NULL;
+  f.data_host = q;
+  CHECK(rc_frame_bytes(&d, &f, &b_host) == RC_OK && b_host > b_dev);
+  d.frame_memory = RC_MEMORY_SLOTS;
+  CHECK(rc_frame_validate(&d, &f) == RC_EINVAL && rc_last_error()[0]);
+  f.n_bins = 0;
+  CHECK(rc_frame_bytes(&d, &f, &b_dev) == RC_EINVAL);
+  free(q);
+  free(vel);
   void* plan = NULL;
   d.hbm_budget_bytes = 1;
   CHECK(rc_plan_create(&d, &plan) == RC_ENOMEM && plan == NULL);
