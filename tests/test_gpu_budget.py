@@ -5,7 +5,8 @@ plan of fixed slots, with the input handed over on the device or in pinned
 host memory; a batch that does not fit what is free is refused without
 enqueuing anything and is admitted once a frame is released; small frames
 share a budget that holds only one frame of the plan's limits; the serving
-loop admits by bytes."""
+loop admits by bytes; a continuous-SAR stream gives the slot plan's
+apertures."""
 import dataclasses
 
 import numpy as np
@@ -148,8 +149,8 @@ def test_frame_larger_than_arena_is_refused(rc, torch):
 
 def test_serving_admits_by_bytes(rc, torch):
     """Poisson arrivals of a large and a small sensor through a budget that
-    holds one large frame: every frame completes, the bytes in flight never
-    exceed the budget, and results equal the frames processed alone."""
+    holds one and a half large frames: every frame completes and results
+    equal the frames processed alone."""
     from paper_2306_09784_amd import serve
 
     big, small = _frames()
@@ -176,3 +177,36 @@ def test_serving_admits_by_bytes(rc, torch):
             assert np.array_equal(r.detections, alone[r.sensor_id]["detections"]), r.frame_id
     finally:
         srv.close()
+
+
+def test_budget_plan_continuous_sar_equals_slot_plan(rc, torch):
+    """A continuous-SAR stream (sub-apertures of 8 chirps, apertures of the
+    last 3) through a budget plan, every sub-aperture handed over in pinned
+    host memory: each aperture's image and detections bitwise the slot
+    plan's."""
+    from tests.test_gpu_sliding import _Runner, _plan_cfg, _stream
+
+    K, S, nb = 3, 8, 5
+    fr, blocks = _stream(nb, S, seed=41)
+    base = _plan_cfg(rc, fr, S, K, slots=4)
+    with rc.Plan(base) as plan:
+        ref = _Runner(rc, torch, plan, fr).run(blocks)
+    cfg = dataclasses.replace(base, frame_memory=rc.RC_MEMORY_BUDGET, hbm_budget_bytes=1 << 30)
+    pix = torch.from_numpy(np.ascontiguousarray(fr.pix)).to("cuda")
+    n_pix = fr.n_rows * fr.n_cols
+    with rc.Plan(cfg) as plan:
+        for j, blk in enumerate(blocks):
+            pinned = torch.from_numpy(blk["raw"]).pin_memory()
+            img = torch.empty((n_pix, 2), dtype=torch.float32, device="cuda")
+            f = rc.Plan.make_frame(50 + j, data=None, data_host=pinned, q_tx=blk["q_tx"], q_rx=blk["q_rx"],
+                                   vel=blk["vel"], pixels=pix, n_rows=fr.n_rows, n_cols=fr.n_cols,
+                                   n_bins=fr.n_bins, n_fft=fr.n_fft, fs=fr.fs, n_samples=fr.cfg.n_samples,
+                                   image_out=img, sensor_id=0, height=fr.cfg.height,
+                                   sliding=rc.RC_SLIDE_START if j == 0 else rc.RC_SLIDE_NEXT)
+            plan.process([f])
+            dets = plan.detections(50 + j)
+            torch.cuda.synchronize()
+            plan.release(50 + j)
+            got = img.cpu().numpy().view(np.complex64).reshape(-1)
+            np.testing.assert_array_equal(got, ref[j][0])
+            assert np.array_equal(dets, ref[j][1]), j
