@@ -772,13 +772,15 @@ def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=F
     return out
 
 
-def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=64, max_batch=32):
+def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots=64, max_batch=32,
+            precision="fp32-split"):
     """Poisson arrivals from all sensors at `load` x the measured batch capacity,
     continuous batching over the plan's slots (at most max_batch frames per
     batch, so a second batch can be admitted while one runs), two streams."""
     from paper_2306_09784_amd import serve
 
-    srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots), n_streams=2)
+    srv = serve.Server(mixed_plan_config(rc, synth, sensors, slots, precision=getattr(rc, FORMS[precision])),
+                       n_streams=2)
     try:
         with no_gc():
             res = serve.run_poisson(srv, sensors, rate_hz=load * capacity_fps, duration_s=duration_s,
@@ -786,20 +788,23 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
     finally:
         srv.close()
     res["load"] = load
-    res["precision"] = "fp32-split"
+    res["precision"] = precision
     res["realtime_bound_ms"] = 1024 * synth.RADAR["t_pri"] * 1e3
     return res
 
 
 def serving_legs(rc, synth, torch, sensors, capacity_fps, seconds):
-    """Poisson serving at 70 % of the uploaded batch capacity (half the time),
-    at 50 % (a quarter), and at 70 % with admission by bytes (a quarter)."""
-    res = serving(rc, synth, torch, sensors, capacity_fps, seconds / 2)
+    """Poisson serving at 70 % of the uploaded batch capacity (0.4 of the
+    time), at 50 % (0.2), at 70 % with admission by bytes (0.2), and at 70 %
+    in the paper's plain single-precision form (0.2)."""
+    res = serving(rc, synth, torch, sensors, capacity_fps, 0.4 * seconds)
     progress("serving done")
-    res["at_half_load"] = serving(rc, synth, torch, sensors, capacity_fps, seconds / 4, load=0.5)
+    res["at_half_load"] = serving(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds, load=0.5)
     progress("serving at half load done")
-    res["by_bytes"] = serving_budget(rc, synth, torch, sensors, capacity_fps, seconds / 4)
+    res["by_bytes"] = serving_budget(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds)
     progress("serving by bytes done")
+    res["plain_fp32"] = serving(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds, precision="fp32")
+    progress("serving in the plain form done")
     return res
 
 
