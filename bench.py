@@ -47,20 +47,23 @@ PUBLISHED_FP32_TFLOPS = 157.3
 def alg2_cost(chg: int):
     """(algorithmic FP32 flops, issue slots) per back-projection term.
 
-    Flops (FMA = 2; sqrt, sin, cos, floor/fraction = 1): squared RX distance
-    and its square root 6, path sum 1, index 2, index fraction 1, sin + cos 2
-    (the hardware takes the phase in turns and reduces it), interpolation 4
-    (the table holds value and slope), complex multiply-accumulate 8 = 24 per
-    term, plus the TX distance with the pixel's correction term (7) once per
-    group of chg channels that share a TX position.
-    Slots: 11 add/mul/FMA (squared distance 3, path sum 1, index 1,
-    interpolation 2, multiply-accumulate 4), 2 half-rate (index conversion
-    and fraction; the table load takes the bin index itself, which the
-    buffer descriptor's 16-byte stride scales) and 3 transcendentals (sqrt,
-    sin, cos) per term, plus 4 add/FMA and 1 sqrt per TX distance.
+    Flops, those of the algorithm as written (FMA = 2; sqrt, sin, cos,
+    floor/fraction = 1): squared RX distance and its square root 6, path sum
+    1, index 2, index fraction 1, sin + cos 2 (the hardware takes the phase in
+    turns and reduces it), interpolation 4 (value and slope of the segment),
+    complex multiply-accumulate 8 = 24 per term, plus the TX distance with the
+    pixel's correction term (7) once per group of chg channels that share a
+    TX position.
+    Slots, those of the compiled loop: 11 add/mul/FMA (squared distance 3,
+    path sum 1, index 1, interpolation 2, multiply-accumulate 4), 1 half-rate
+    (the index conversion: the table holds each segment's intercept and
+    slope in the fractional index itself, so no fraction is formed, and the
+    table load takes the bin index, which the buffer descriptor's 16-byte
+    stride scales) and 3 transcendentals (sqrt, sin, cos) per term, plus 4
+    add/FMA and 1 sqrt per TX distance.
     """
     flops = 24.0 + 7.0 / chg
-    slots = 11.0 + 2 * HALF_SLOTS + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
+    slots = 11.0 + HALF_SLOTS + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
     return flops, slots
 
 
@@ -1026,7 +1029,7 @@ def main(argv=None):
             "frac": achieved / peak,
             "peak_note": "peak = the VALU issue ceiling of this loop's instruction mix: 256 CUs x 128 FP32 "
                          "lanes/clock x 2.4 GHz over the issue slots one term needs (full-rate add/FMA 1, "
-                         "conversion and fraction 2, sqrt/sin/cos 4), times its algorithmic flops per term",
+                         "index conversion 2, sqrt/sin/cos 4), times its algorithmic flops per term",
             "published_fp32_peak": PUBLISHED_FP32_TFLOPS,
             "frac_of_published_fp32_peak": achieved / PUBLISHED_FP32_TFLOPS,
             "slots_per_term": slots,

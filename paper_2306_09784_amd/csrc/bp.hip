@@ -12,17 +12,19 @@
 // the interpolation table by range compression.
 //
 // gfx950 mapping.  The loop is bound by VALU issue (three quarter-rate
-// transcendentals per term: sqrt, sin, cos; two half-rate instructions, the
-// index conversion and its fraction; eleven full-rate adds and FMAs), so the
-// design minimises instructions per term:
+// transcendentals per term: sqrt, sin, cos; the half-rate index conversion;
+// eleven full-rate adds and FMAs), so the design minimises instructions per
+// term:
 //  * geometry is in aperture-local wavelength units, so a path length is its
 //    carrier phase in turns and goes straight into the hardware sin/cos
 //    (which take turns);
 //  * a squared distance is |P|^2 + |q|^2 - 2 P.q: two FMAs and an add with the
 //    per-row uniforms (-2 q, |q|^2), read with scalar loads;
 //  * channels sharing a TX position evaluate d_tx once per group;
-//  * the table holds (s[k], s[k+1] - s[k]) so one 16-byte buffer load and two
-//    FMAs interpolate a term; loads go through a per-row buffer descriptor, so
+//  * the table holds each segment's intercept and slope in the bin index f
+//    (A = s[k] - k D, D = s[k+1] - s[k]), so one 16-byte buffer load and two
+//    FMAs with f itself interpolate a term, with no fraction of f; loads go
+//    through a per-row buffer descriptor, so
 //    an index outside the row reads zeros instead of faulting, and where the
 //    index is proven in range the load takes the bin index itself (the
 //    descriptor's 16-byte stride scales it: no shift per term);
@@ -141,7 +143,7 @@ __device__ __forceinline__ Leg<FORM> leg(const float4 q, const float4 p, const P
 template <int U>
 struct Stage {
   u32x4 e[U];
-  float phi[U];
+  float f[U];  // fractional bin index of the term
   float turn[U];
 };
 
@@ -229,14 +231,11 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
         turn = d_hyp;
       }
       int i;
-      if (CHECKED) {
-        const float fl = floorf(f);
-        st.phi[j] = f - fl;
-        i = (f >= 0.f && f <= nbm1) ? (int)fl : -1;  // -1: outside the descriptor -> zeros
-      } else {
+      if (CHECKED)
+        i = (f >= 0.f && f <= nbm1) ? (int)f : -1;  // -1: outside the descriptor -> zeros
+      else
         i = (int)f;                                  // f >= 0 here: truncation is floor
-        st.phi[j] = __builtin_amdgcn_fractf(f);
-      }
+      st.f[j] = f;
       st.turn[j] = turn;
       if (CHECKED) {
         // i = -1 reads past the descriptor's range: zeros, no access
@@ -264,8 +263,9 @@ __device__ __forceinline__ void bp_terms(const BpFrame& a, int row_begin, int ro
       // path length in wavelengths goes in without a fraction
       const float sn = __builtin_amdgcn_sinf(st.turn[j]);  // sin(2 pi turn)
       const float cs = __builtin_amdgcn_cosf(st.turn[j]);
-      const float vr = fmaf(st.phi[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
-      const float vi = fmaf(st.phi[j], __uint_as_float(st.e[j].w), __uint_as_float(st.e[j].y));
+      // the segment's intercept + f x slope (zeros outside the row: 0)
+      const float vr = fmaf(st.f[j], __uint_as_float(st.e[j].z), __uint_as_float(st.e[j].x));
+      const float vi = fmaf(st.f[j], __uint_as_float(st.e[j].w), __uint_as_float(st.e[j].y));
       // (cs - i sn) (vr + i vi); the sub-aperture form keeps one accumulator pair
       if (SUMS == 1 && (((U == 1) ? par : j) & 1)) {
         re1 = fmaf(cs, vr, re1);

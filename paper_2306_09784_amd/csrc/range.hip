@@ -10,9 +10,9 @@
 // radix-2 stages.  The first pass reads the windowed samples straight from
 // HBM (coalesced: lane j of a row reads samples j + r n/16) and treats the
 // zero padding as zeros without loading it; the last pass keeps only the
-// n_bins bins that are written, directly in the interleaved (value, slope)
-// layout that back-projection gathers with one 16-byte load per term, with
-// the chirp window w_sar[m] folded in.  Pass p of radix R at stride Ns
+// n_bins bins that are written, directly in the interleaved (intercept,
+// slope) layout that back-projection gathers with one 16-byte load per term,
+// with the chirp window w_sar[m] folded in.  Pass p of radix R at stride Ns
 // multiplies input r of butterfly b by W_{Ns R}^{(b mod Ns) r} (evaluated by the
 // hardware sine and cosine, which take their argument in turns: the argument
 // (b mod Ns) r / (Ns R) is exact in single precision, so each twiddle carries
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void range_compress_kernel(RangeMulti m) 
   for (int k = j; k < a.n_bins; k += F::T) {
     const float2 x = buf[pad(k)];
     const float2 d = (k < last) ? csub(buf[pad(k + 1)], x) : make_float2(0.f, 0.f);
-    dst[k] = make_float4(w * x.x, w * x.y, w * d.x, w * d.y);
+    dst[k] = table_entry(w, x, d, k);
     if (spec) spec[k] = x;
   }
 }
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void spectrum_pairs_kernel(PairMulti m) {
   const float w = a.w_sar[row / a.n_ch];
   const float2 x = a.spec[i];
   const float2 d = (k < a.n_bins - 1) ? csub(a.spec[i + 1], x) : make_float2(0.f, 0.f);
-  a.pairs[i] = make_float4(w * x.x, w * x.y, w * d.x, w * d.y);
+  a.pairs[i] = table_entry(w, x, d, k);
 }
 
 }  // namespace

@@ -27,8 +27,9 @@
 // wave w owning k2 in [16 w, 16 w + 16) in both stages; the row's data are read
 // by every wave (the L1 and L2 serve the repeats); Y crosses to the stage-2
 // layout through LDS; the kept bins go through LDS once more to be written as
-// the interpolation table (w_sar[m] s[k], w_sar[m] (s[k+1] - s[k])) of
-// back-projection, 16 bytes per bin, coalesced.  Workgroups stay resident and
+// the interpolation table of back-projection (intercept and slope of the
+// segment from bin k to k + 1, the chirp window folded in), 16 bytes per
+// bin, coalesced.  Workgroups stay resident and
 // loop over the rows of the launch, loading each row one trip ahead; the
 // twiddle operands are formed where they are used (from the hardware sine and
 // cosine), which costs a few transcendentals per output and keeps the
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(64 * Mfft<LOG2N>::W) void range_mfma_kernel(RangeMu
     for (int k = threadIdx.x; k < a.n_bins; k += 64 * F::W) {
       const float2 v = sb[k];
       const float2 d = k < last ? make_float2(sb[k + 1].x - v.x, sb[k + 1].y - v.y) : make_float2(0.f, 0.f);
-      dst[k] = make_float4(wv * v.x, wv * v.y, wv * d.x, wv * d.y);
+      dst[k] = table_entry(wv, v, d, k);
       if (spec) spec[k] = v;
     }
     __syncthreads();

@@ -30,6 +30,19 @@ __device__ __forceinline__ int multi_frame(const M& m, int w) {
   return __builtin_amdgcn_readfirstlane(fi);
 }
 
+// Entry k of back-projection's interpolation table (one row: one chirp and
+// channel).  On the segment from bin k to k + 1 the windowed spectrum is
+// w s[k] + (f - k) w (s[k+1] - s[k]) = A + f D with D = w (s[k+1] - s[k]) and
+// A = w s[k] - k D, so a term at fractional bin index f in [k, k + 1] costs
+// one FMA per component with f itself: no fraction of f is formed.  The last
+// kept bin has D = 0.  A is rounded once (from w s[k] and k D); its error,
+// half an ulp of about k |D|, is of the size of the rounding that f already
+// carries at bin k.
+__device__ __forceinline__ float4 table_entry(float w, float2 s, float2 d, int k) {
+  const float dx = w * d.x, dy = w * d.y, kf = (float)k;
+  return make_float4(fmaf(-kf, dx, w * s.x), fmaf(-kf, dy, w * s.y), dx, dy);
+}
+
 // Per-frame geometry from mapped pinned host memory (src, the device address
 // of the staging buffer) to device memory, n16 16-byte units.
 struct UploadArgs {
@@ -42,9 +55,8 @@ hipError_t launch_upload(const UploadMulti& m, hipStream_t s);
 
 // Range compression (beat signal -> beat spectrum): windowed, zero-padded
 // radix-2 decimation-in-time FFT per (chirp, channel) row in LDS, cropped to
-// n_bins.  Writes the interpolation table of back-projection: for bin k the
-// float4 (w s[k], w (s[k+1] - s[k])) with w = w_sar[row / n_ch] and a zero
-// slope for the last kept bin; optionally also the plain spectrum s.
+// n_bins.  Writes the interpolation table of back-projection (table_entry
+// below); optionally also the plain spectrum s.
 struct RangeArgs {
   const float2* raw;      // [rows][n_s]
   const float* w_range;   // [n_s]
