@@ -797,17 +797,21 @@ def serving(rc, synth, torch, sensors, capacity_fps, duration_s, load=0.7, slots
 
 
 def serving_legs(rc, synth, torch, sensors, capacity_fps, seconds):
-    """Poisson serving at 70 % of the uploaded batch capacity (0.4 of the
-    time), at 50 % (0.2), at 70 % with admission by bytes (0.2), and at 70 %
-    in the paper's plain single-precision form (0.2)."""
-    res = serving(rc, synth, torch, sensors, capacity_fps, 0.4 * seconds)
+    """Poisson serving at 70 % of the uploaded batch capacity (0.3 of the
+    time), at 50 % (0.15), at 70 % with admission by bytes (0.15), at 70 % in
+    the paper's plain single-precision form (0.2), and at 70 % with the
+    spectrum formed on the matrix cores in FP16 (0.2)."""
+    res = serving(rc, synth, torch, sensors, capacity_fps, 0.3 * seconds)
     progress("serving done")
-    res["at_half_load"] = serving(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds, load=0.5)
+    res["at_half_load"] = serving(rc, synth, torch, sensors, capacity_fps, 0.15 * seconds, load=0.5)
     progress("serving at half load done")
-    res["by_bytes"] = serving_budget(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds)
+    res["by_bytes"] = serving_budget(rc, synth, torch, sensors, capacity_fps, 0.15 * seconds)
     progress("serving by bytes done")
     res["plain_fp32"] = serving(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds, precision="fp32")
     progress("serving in the plain form done")
+    res["fp16_spectrum"] = serving(rc, synth, torch, sensors, capacity_fps, 0.2 * seconds,
+                                   precision="fp16-spectrum")
+    progress("serving with the FP16 matrix-core spectrum done")
     return res
 
 

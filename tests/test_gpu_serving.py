@@ -28,14 +28,14 @@ def rc():
     return mod
 
 
-def _sensors(torch, n):
+def _sensors(torch, n, samples=(32, 64)):
     from paper_2306_09784_amd import serve
 
     rng = np.random.default_rng(41)
     out = []
     for i in range(n):
         cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name=f"s{i}",
-                                  n_samples=int(rng.choice([32, 64])), n_chirps=int(rng.choice([8, 16])),
+                                  n_samples=int(rng.choice(samples)), n_chirps=int(rng.choice([8, 16])),
                                   n_rx=int(rng.choice([2, 4, 8])), nx=int(rng.choice([24, 40])),
                                   ny=int(rng.choice([1, 24, 33])), box=(-4.0, 4.0, 1.5, 7.0), seed=500 + i)
         fr = synth.make_frame(cfg, frame_index=i)
@@ -44,11 +44,16 @@ def _sensors(torch, n):
     return out
 
 
-def test_poisson_serving_results_equal_alone(rc, torch):
+@pytest.mark.parametrize("precision", ["RC_PREC_FP32", "RC_PREC_FP16"])
+def test_poisson_serving_results_equal_alone(rc, torch, precision):
+    """Either form: plain single precision, and the spectrum formed on the
+    matrix cores in FP16 (DFT lengths 256 and 512 here, the shortest it takes)."""
     from paper_2306_09784_amd import serve
 
-    sensors = _sensors(torch, 6)
-    cfg = SC.plan_config(rc, [s.frame for s in sensors], max_frames_in_flight=4)
+    fp16 = precision == "RC_PREC_FP16"
+    sensors = _sensors(torch, 6, samples=(128, 256) if fp16 else (32, 64))
+    cfg = SC.plan_config(rc, [s.frame for s in sensors], max_frames_in_flight=4,
+                         precision=getattr(rc, precision))
     srv = serve.Server(cfg, n_streams=2, keep_images=True)
     peak = [0]
     orig_submit = srv.submit
