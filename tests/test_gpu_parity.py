@@ -319,6 +319,25 @@ def test_bp_parity_small_lattices(rc, torch, n_rows, n_cols):
     _check_image(f"lattice_{n_rows}x{n_cols}", fr, out["image"], ora, PLAIN)
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("n_samples,n_chirps,n_rx,n_rows,n_cols", [
+    (32, 1, 1, 1, 1),       # one chirp of one channel, one pixel (the chirp window is one sample)
+    (64, 1, 4, 1, 64),      # one chirp, one row of pixels
+    (2048, 3, 2, 9, 17),    # the longest DFT (4096 points), a ragged lattice
+])
+def test_degenerate_and_longest_shapes(rc, torch, precision, n_samples, n_chirps, n_rx, n_rows, n_cols):
+    """Degenerate frames and the longest range DFT, raw input end to end
+    against the oracle's image."""
+    cfg = dataclasses.replace(synth.CONFIGS["plain-small"], name="deg", n_samples=n_samples, n_chirps=n_chirps,
+                              n_rx=n_rx, nx=n_cols, ny=n_rows, box=(-3.0, 3.0, 2.0, 5.0), n_targets=2,
+                              noise=True, seed=19)
+    fr = synth.make_frame(cfg)
+    with rc.Plan(SC.plan_config(rc, [fr], precision=precision)) as plan:
+        out = SC.run_gpu(rc, plan, fr, torch)
+    ora = SC.run_oracle(fr, cfar=None)
+    _check_image(f"shape_{n_samples}x{n_chirps}x{n_rx}_{n_rows}x{n_cols}", fr, out["image"], ora, precision)
+
+
 # ---------------------------------------------------------------------------
 # end to end
 # ---------------------------------------------------------------------------
