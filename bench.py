@@ -729,21 +729,50 @@ def batched_mixed_median(rc, synth, torch, sensors, repeats=3, **kw):
     med["resident_fp32"] = {"frames_per_s": res[len(res) // 2]["frames_per_s"],
                             "frames_per_s_runs": [r["frames_per_s"] for r in res],
                             "bp_terms_per_s_incl_all_stages": res[len(res) // 2]["bp_terms_per_s_incl_all_stages"]}
+    # the chirp split tuned per size class (rc_plan_tune) on the resident batches
+    t0 = time.perf_counter()
+    table = tune_sensors(rc, synth, sensors)
+    t_tune = time.perf_counter() - t0
+    res = sorted((batched_mixed(rc, synth, torch, sensors, resident=True, tuning=table, **kw)
+                  for _ in range(repeats)), key=lambda r: r["frames_per_s"])
+    med["resident_tuned"] = {"frames_per_s": res[len(res) // 2]["frames_per_s"],
+                             "frames_per_s_runs": [r["frames_per_s"] for r in res],
+                             "classes": len(table),
+                             "classes_changed": sum(e["chirp_blocks"] != e["default_blocks"] for e in table),
+                             "tuning_s": t_tune}
     return med
 
 
-def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=False, precision="fp32-split"):
+def tune_sensors(rc, synth, sensors, precision="fp32-split"):
+    """rc_plan_tune over one frame of every sensor (their cubes resident): the
+    table of chirp splits per size class."""
+    cfg = mixed_plan_config(rc, synth, sensors, 2, precision=getattr(rc, FORMS[precision]))
+    descs = []
+    for i, sn in enumerate(sensors):
+        fr = sn.frame
+        descs.append(rc.Plan.make_frame(i + 1, data=sn.raw_dev, q_tx=fr.q_tx, q_rx=fr.q_rx, vel=fr.vel,
+                                        pixels=sn.pix_dev, n_rows=fr.n_rows, n_cols=fr.n_cols, n_bins=fr.n_bins,
+                                        n_fft=fr.n_fft, fs=fr.fs, n_samples=fr.cfg.n_samples))
+    with rc.Plan(cfg) as plan:
+        return plan.tune(descs)
+
+
+def batched_mixed(rc, synth, torch, sensors, n_frames=1024, batch=32, resident=False, precision="fp32-split",
+                  tuning=None):
     """Frames of mixed sizes in batches of `batch` frames per rc_process_batch
     (one back-projection launch per TX-group width and 16 frames), each batch
     including the pinned-memory upload of its beat cubes (resident=False) or
     with every cube already in HBM (resident=True).  Two batches are in
     flight on two streams: the host prepares and enqueues the next batch while
-    the GPU processes the current one."""
+    the GPU processes the current one.  tuning: a table of chirp splits per
+    size class (rc_plan_tune) installed in the plan first."""
     from paper_2306_09784_amd import serve
 
     srv = serve.Server(mixed_plan_config(rc, synth, sensors, 2 * batch, precision=getattr(rc, FORMS[precision])),
                        n_streams=2, resident=resident)
     try:
+        if tuning:
+            srv.plan.set_tuning(tuning)
         order = [sensors[i % len(sensors)] for i in range(n_frames)]
         with no_gc():
             # warm-up batch (after the collector ran: no pause before the timed batches)

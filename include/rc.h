@@ -261,7 +261,10 @@ rc_status rc_plan_slot_bytes(const rc_plan_desc* desc, int64_t* bytes);
  * rc_frame_validate) takes from the arena of a RC_MEMORY_BUDGET plan with this
  * descriptor: its interpolation table, geometry, pixel tables, partial images,
  * image (if image_out is NULL), CFAR buffers, detection list, recheck buffers
- * and, with data_host, its input.  Host only, no GPU. */
+ * and, with data_host, its input.  Host only, no GPU.  The partial images
+ * are counted for the default chirp split (rc_plan_tune below); a plan whose
+ * tuning table gives the frame's class more blocks takes n_rows x n_cols x 8
+ * bytes more per extra block from its arena. */
 rc_status rc_frame_bytes(const rc_plan_desc* desc, const rc_frame* frame, int64_t* bytes);
 
 /* Checks one frame (host) against a plan descriptor (host) exactly as
@@ -292,6 +295,53 @@ rc_status rc_frame_validate(const rc_plan_desc* desc, const rc_frame* frame);
  * outside [0, n_bins - 1] are zero, not an error. */
 rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
                            void* stream);
+
+/* Plan-time tuning of back-projection's chirp split, per size class.
+ * Back-projection divides a frame's chirps into blocks (work items of one
+ * launch) whose partial images are summed in block order.  By default the
+ * block count follows a rule of the frame's size: about ten generations of
+ * the GPU's waves, at least 512 chirp x channel rows a block, at most 16
+ * blocks.  A size class is a frame's (n_rows, n_cols, n_chirps, n_channels).
+ * The block count changes only the order in which a pixel's terms are
+ * summed: a tuned class's images differ from the rule's by rounding, and
+ * stay bitwise reproducible within the plan (and in any plan given the same
+ * table), whatever batch a frame arrives in.  Sub-apertures of a continuous
+ * stream always take the rule. */
+typedef struct rc_tuning_entry {
+  int32_t n_rows, n_cols;         /* the size class: lattice, ...                 */
+  int32_t n_chirps, n_channels;   /* ... chirps and channels                      */
+  int32_t chirp_blocks;           /* blocks the class takes, 1 .. min(16, n_chirps)*/
+  int32_t default_blocks;         /* the rule's count (rc_plan_tune writes it)    */
+  float ms_default;               /* rc_plan_tune: median frame time, rule's split */
+  float ms_chosen;                /* rc_plan_tune: median frame time, chosen split */
+} rc_tuning_entry;
+
+/* Measures, for each size class among frames (host array; sub-apertures
+ * refused), the device time per frame on stream of a batch of min(4, free
+ * slots) copies of the class's first frame (rc_process_batch; one untimed
+ * batch, then the median of three), so that the split suits frames that
+ * share the GPU, with the rule's block count and with a quarter, half,
+ * twice and four times as many (within 1 .. min(16, n_chirps) and the slots'
+ * partial-image capacity); installs the fastest in the plan when it beats
+ * the rule's by more than 2 % (else the rule's), and writes one entry per
+ * class to out (host, cap entries), *n_out = number of classes.  The first
+ * copy writes the frame's image_out, doppler_out and spectrum_out, the others
+ * their slots' buffers; inputs must stay valid until the call returns.  The
+ * copies take frame ids that no frame in flight has; the plan needs a free
+ * slot and the call synchronizes stream.  RC_EINVAL on a frame the plan refuses, RC_ETRUNC
+ * (nothing measured) when cap is below the number of classes, RC_ENOTREADY
+ * when no slot is free.  Frames already in flight keep their split. */
+rc_status rc_plan_tune(void* plan, const rc_frame* frames, int32_t n_frames, void* stream,
+                       rc_tuning_entry* out, int32_t cap, int32_t* n_out);
+
+/* Installs a tuning table (host; for instance the entries rc_plan_tune wrote
+ * for another plan of the same descriptor): each entry's size class takes
+ * its chirp_blocks; the other fields are ignored.  The table replaces the
+ * plan's; n = 0 clears it.  RC_EINVAL, with the table unchanged, on a class
+ * outside the plan's limits or a block count outside 1 .. min(16, n_chirps)
+ * or beyond the slots' partial-image capacity.  Frames already in flight
+ * keep their split. */
+rc_status rc_plan_set_tuning(void* plan, const rc_tuning_entry* entries, int32_t n);
 
 /* RC_OK if the frame's work is complete, RC_ENOTREADY if not, RC_ENOTFOUND. */
 rc_status rc_poll(void* plan, int64_t frame_id);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -180,6 +181,10 @@ struct Plan {
   // the batches before it; the batch's stream waits for them by an event
   hipStream_t copy_stream = nullptr;
   hipEvent_t copied = nullptr;
+  // back-projection's chirp blocks per size class (n_rows, n_cols, n_chirps,
+  // n_channels), installed by rc_plan_tune / rc_plan_set_tuning; classes not
+  // listed take the rule of rc::bp_chirp_blocks
+  std::map<std::array<int32_t, 4>, int> tuned;
 };
 
 // First fit from the arena; returns the offset or SIZE_MAX when no free range holds len.
@@ -432,7 +437,13 @@ void free_plan(Plan* p) {
 
 // Chirp blocks of a frame's back-projection; a sub-aperture's partial images
 // have `planes` planes each and must fit the slot's partial buffer.
+std::array<int32_t, 4> size_class(const rc_frame& f) { return {f.n_rows, f.n_cols, f.n_chirps, f.n_channels}; }
+
 int frame_chirp_blocks(const Plan* p, const rc_frame& f) {
+  if (f.sliding == RC_SLIDE_OFF && !p->tuned.empty()) {
+    const auto it = p->tuned.find(size_class(f));
+    if (it != p->tuned.end()) return it->second;
+  }
   const int planes = f.sliding != RC_SLIDE_OFF ? p->planes : 1;
   int n_kb = rc::bp_chirp_blocks(f.n_rows, f.n_cols, f.n_chirps, f.n_channels, planes);
   if (f.sliding != RC_SLIDE_OFF && n_kb > 1) {
@@ -1582,6 +1593,138 @@ rc_status rc_frame_release(void* plan, int64_t frame_id) {
     arena_free(p, s->arena_off, s->arena_len);
     s->arena_len = 0;
     s->input = nullptr;
+  }
+  return RC_OK;
+}
+
+// A tuned block count for a class must be one the kernels and the slots take.
+rc_status check_tuning_entry(const Plan* p, const rc_tuning_entry& e) {
+  const rc_plan_desc& d = p->d;
+  if (e.n_rows < 1 || e.n_cols < 1 || (int64_t)e.n_rows * e.n_cols > d.n_pix_max || e.n_chirps < 1 ||
+      e.n_chirps > d.n_chirps_max || e.n_channels < 1 || e.n_channels > d.n_channels_max)
+    return fail(RC_EINVAL, "tuning entry %d x %d pixels, %d chirps, %d channels is outside the plan's limits",
+                e.n_rows, e.n_cols, e.n_chirps, e.n_channels);
+  const int most = std::min(16, e.n_chirps);
+  if (e.chirp_blocks < 1 || e.chirp_blocks > most)
+    return fail(RC_EINVAL, "tuning entry: %d chirp blocks outside [1, %d]", e.chirp_blocks, most);
+  if (e.chirp_blocks > 1 && (int64_t)e.chirp_blocks * e.n_rows * e.n_cols > partial_capacity(d))
+    return fail(RC_EINVAL, "tuning entry: %d chirp blocks exceed the partial-image buffer", e.chirp_blocks);
+  return RC_OK;
+}
+
+rc_status rc_plan_set_tuning(void* plan, const rc_tuning_entry* entries, int32_t n) {
+  g_err.clear();
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p) return fail(RC_EINVAL, "plan is NULL");
+  if (n < 0 || (n > 0 && !entries)) return fail(RC_EINVAL, "bad tuning table");
+  std::map<std::array<int32_t, 4>, int> table;
+  for (int i = 0; i < n; ++i) {
+    const rc_status st = check_tuning_entry(p, entries[i]);
+    if (st != RC_OK) return st;
+    table[{entries[i].n_rows, entries[i].n_cols, entries[i].n_chirps, entries[i].n_channels}] = entries[i].chirp_blocks;
+  }
+  p->tuned = std::move(table);
+  return RC_OK;
+}
+
+rc_status rc_plan_tune(void* plan, const rc_frame* frames, int32_t n_frames, void* stream, rc_tuning_entry* out,
+                       int32_t cap, int32_t* n_out) {
+  g_err.clear();
+  Plan* p = static_cast<Plan*>(plan);
+  if (!p) return fail(RC_EINVAL, "plan is NULL");
+  if (n_frames < 0 || (n_frames > 0 && !frames) || cap < 0 || (cap > 0 && !out) || !n_out)
+    return fail(RC_EINVAL, "bad frame array or output table");
+  // the classes, each probed with its first frame
+  std::vector<std::pair<std::array<int32_t, 4>, int>> classes;
+  for (int i = 0; i < n_frames; ++i) {
+    if (frames[i].sliding != RC_SLIDE_OFF)
+      return fail(RC_EINVAL, "frame %lld: sub-apertures keep the rule's chirp split", (long long)frames[i].frame_id);
+    const rc_status st = validate_frame(p, frames[i]);
+    if (st != RC_OK) return st;
+    const auto key = size_class(frames[i]);
+    if (std::none_of(classes.begin(), classes.end(), [&](const auto& c) { return c.first == key; }))
+      classes.emplace_back(key, i);
+  }
+  *n_out = (int32_t)classes.size();
+  if ((int64_t)classes.size() > cap)
+    return fail(RC_ETRUNC, "%zu size classes, room for %d entries", classes.size(), cap);
+  if (classes.empty()) return RC_OK;
+  // each measurement is a batch of `copies` copies of the class's frame (the
+  // first one with the caller's outputs, the others into their slots), so
+  // that the split is chosen for frames that share the GPU with others
+  const int free_slots = (int)std::count_if(p->slots.begin(), p->slots.end(), [](const Slot& s) { return !s.busy; });
+  if (free_slots < 1) return fail(RC_ENOTREADY, "the plan has no free slot to tune with");
+  const int copies = std::min(4, free_slots);
+  int64_t ids[4];
+  int64_t next_id = INT64_MIN;
+  for (int k = 0; k < copies; ++k) {
+    while (find_slot(p, next_id)) ++next_id;
+    ids[k] = next_id++;
+  }
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  RC_HIP(hipEventCreate(&ev.a));
+  RC_HIP(hipEventCreate(&ev.b));
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  for (size_t c = 0; c < classes.size(); ++c) {
+    const auto key = classes[c].first;
+    rc_frame f[4];
+    for (int k = 0; k < copies; ++k) {
+      f[k] = frames[classes[c].second];
+      f[k].frame_id = ids[k];
+      if (k > 0) {
+        f[k].image_out = nullptr;
+        f[k].doppler_out = nullptr;
+        f[k].spectrum_out = nullptr;
+      }
+    }
+    p->tuned.erase(key);
+    const int k0 = frame_chirp_blocks(p, f[0]);
+    std::vector<int> cand{k0};
+    for (const int k : {k0 / 4, k0 / 2, 2 * k0, 4 * k0}) {
+      rc_tuning_entry e{key[0], key[1], key[2], key[3], k, k0, 0.f, 0.f};
+      if (k >= 1 && std::find(cand.begin(), cand.end(), k) == cand.end() && check_tuning_entry(p, e) == RC_OK)
+        cand.push_back(k);
+    }
+    g_err.clear();
+    std::vector<float> med(cand.size());
+    for (size_t j = 0; j < cand.size(); ++j) {
+      p->tuned[key] = cand[j];
+      float t[3];
+      for (int run = 0; run < 4; ++run) {
+        const hipError_t e0 = hipEventRecord(ev.a, hs);
+        rc_status st = e0 == hipSuccess ? rc_process_batch(p, f, copies, stream)
+                                        : fail(RC_EHIP, "tuning: %s", hipGetErrorString(e0));
+        if (st == RC_OK) {
+          hipError_t e = hipEventRecord(ev.b, hs);
+          if (e == hipSuccess) e = hipEventSynchronize(ev.b);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.a, ev.b);
+          for (int k = 0; k < copies; ++k) {
+            const rc_status rel = rc_frame_release(p, ids[k]);
+            if (st == RC_OK) st = rel;
+          }
+          if (e != hipSuccess) st = fail(RC_EHIP, "tuning: %s", hipGetErrorString(e));
+          if (run > 0) t[run - 1] = ms / copies;
+        }
+        if (st != RC_OK) {
+          p->tuned.erase(key);
+          return st;
+        }
+      }
+      std::sort(t, t + 3);
+      med[j] = t[1];
+    }
+    size_t best = 0;
+    for (size_t j = 1; j < cand.size(); ++j)
+      if (med[j] < 0.98f * med[0] && med[j] < med[best]) best = j;
+    p->tuned[key] = cand[best];
+    out[c] = rc_tuning_entry{key[0], key[1], key[2], key[3], cand[best], k0, med[0], med[best]};
   }
   return RC_OK;
 }

@@ -112,11 +112,18 @@ class rc_detection(C.Structure):
 DETECTION_DTYPE = np.dtype([("pixel", "<i4"), ("power", "<f4"), ("threshold", "<f4"),
                             ("flags", "<u4")])
 
+
+class rc_tuning_entry(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("n_chirps", C.c_int32), ("n_channels", C.c_int32),
+                ("chirp_blocks", C.c_int32), ("default_blocks", C.c_int32), ("ms_default", C.c_float),
+                ("ms_chosen", C.c_float)]
+
 #: every entry point declared in include/rc.h
 ENTRY_POINTS = [
     "rc_plan_create", "rc_plan_slot_bytes", "rc_frame_bytes", "rc_frame_validate", "rc_process_batch", "rc_poll", "rc_detections",
     "rc_image", "rc_stage_times", "rc_frame_release", "rc_plan_destroy", "rc_last_error", "rc_grid_cartesian",
-    "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar", "rc_process_frame_static",
+    "rc_grid_polar_params", "rc_grid_polar", "rc_resample_polar", "rc_process_frame_static", "rc_plan_tune",
+    "rc_plan_set_tuning",
 ]
 
 
@@ -159,6 +166,9 @@ def _load():
         "rc_resample_polar": (C.c_int, [vp, i32, i32, C.c_double, C.c_double, C.c_double, C.c_double,
                                         C.c_double, C.c_double, vp, i64, vp, vp]),
         "rc_process_frame_static": (C.c_int, [C.POINTER(rc_plan_desc), C.POINTER(rc_frame), vp, i64, vp, vp]),
+        "rc_plan_tune": (C.c_int, [vp, C.POINTER(rc_frame), i32, vp, C.POINTER(rc_tuning_entry), i32,
+                                   C.POINTER(C.c_int32)]),
+        "rc_plan_set_tuning": (C.c_int, [vp, C.POINTER(rc_tuning_entry), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -413,3 +423,27 @@ class Plan:
 
     def release(self, frame_id: int):
         check(lib.rc_frame_release(self.handle, frame_id), "rc_frame_release")
+
+    _TUNING_KEYS = ("n_rows", "n_cols", "n_chirps", "n_channels", "chirp_blocks", "default_blocks", "ms_default",
+                    "ms_chosen")
+
+    def tune(self, frames, stream=None) -> list:
+        """rc_plan_tune: measures the chirp split of each size class among
+        `frames` (rc_frame structs) and installs the fastest; returns one dict
+        per class."""
+        arr = (rc_frame * len(frames))(*frames)
+        cap = max(1, len(frames))
+        out = (rc_tuning_entry * cap)()
+        n = C.c_int32()
+        check(lib.rc_plan_tune(self.handle, arr, len(frames), _stream_handle(stream), out, cap, C.byref(n)),
+              "rc_plan_tune")
+        return [{k: getattr(out[i], k) for k in self._TUNING_KEYS} for i in range(n.value)]
+
+    def set_tuning(self, entries) -> None:
+        """rc_plan_set_tuning: installs a table of dicts with the class keys
+        and chirp_blocks (the other keys are ignored); [] clears it."""
+        arr = (rc_tuning_entry * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            for k in self._TUNING_KEYS[:5]:
+                setattr(arr[i], k, int(e[k]))
+        check(lib.rc_plan_set_tuning(self.handle, arr, len(entries)), "rc_plan_set_tuning")

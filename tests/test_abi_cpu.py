@@ -49,8 +49,8 @@ _LAYOUT_C = r"""
 #include "rc.h"
 #define P(T, F) printf(#T "." #F " %zu\n", offsetof(T, F));
 int main(void) {
-  printf("rc_radar %zu\nrc_plan_desc %zu\nrc_frame %zu\nrc_detection %zu\n",
-         sizeof(rc_radar), sizeof(rc_plan_desc), sizeof(rc_frame), sizeof(rc_detection));
+  printf("rc_radar %zu\nrc_plan_desc %zu\nrc_frame %zu\nrc_detection %zu\nrc_tuning_entry %zu\n",
+         sizeof(rc_radar), sizeof(rc_plan_desc), sizeof(rc_frame), sizeof(rc_detection), sizeof(rc_tuning_entry));
   P(rc_plan_desc, radar) P(rc_plan_desc, n_pix_max) P(rc_plan_desc, range_window)
   P(rc_plan_desc, range_kaiser_beta) P(rc_plan_desc, sar_kaiser_beta) P(rc_plan_desc, precision) P(rc_plan_desc, doppler)
   P(rc_plan_desc, cfar_pfa) P(rc_plan_desc, max_rechecks) P(rc_plan_desc, hbm_budget_bytes) P(rc_plan_desc, stage_timing)
@@ -58,6 +58,7 @@ int main(void) {
   P(rc_frame, fs) P(rc_frame, input_kind) P(rc_frame, data) P(rc_frame, pixels)
   P(rc_frame, n_rows) P(rc_frame, image_out) P(rc_frame, spectrum_out) P(rc_frame, height) P(rc_frame, sliding) P(rc_frame, w_sar) P(rc_frame, f_doppler)
   P(rc_detection, threshold) P(rc_detection, flags)
+  P(rc_tuning_entry, n_channels) P(rc_tuning_entry, chirp_blocks) P(rc_tuning_entry, ms_chosen)
   return 0;
 }
 """
@@ -75,6 +76,7 @@ def test_ctypes_layout_matches_header(rc, tmp_path):
     assert int(got["rc_plan_desc"]) == C.sizeof(rc.rc_plan_desc)
     assert int(got["rc_frame"]) == C.sizeof(rc.rc_frame)
     assert int(got["rc_detection"]) == C.sizeof(rc.rc_detection) == rc.DETECTION_DTYPE.itemsize
+    assert int(got["rc_tuning_entry"]) == C.sizeof(rc.rc_tuning_entry) == 32
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
