@@ -318,7 +318,8 @@ typedef struct rc_tuning_entry {
 
 /* Measures, for each size class among frames (host array; sub-apertures
  * refused), the device time per frame on stream of a batch of min(4, free
- * slots) copies of the class's first frame (rc_process_batch; one untimed
+ * slots) copies of the class's first frame (fewer when an HBM-budget arena
+ * holds fewer; rc_process_batch; one untimed
  * batch, then the median of three), so that the split suits frames that
  * share the GPU, with the rule's block count and with a quarter, half,
  * twice and four times as many (within 1 .. min(16, n_chirps) and the slots'

@@ -1692,25 +1692,35 @@ rc_status rc_plan_tune(void* plan, const rc_frame* frames, int32_t n_frames, voi
         cand.push_back(k);
     }
     g_err.clear();
+    // most blocks (most partial-image bytes) first: under an HBM budget the
+    // batch shrinks there until it fits, and every later candidate fits too
+    std::sort(cand.begin(), cand.end(), [](int x, int y) { return x > y; });
+    int n = copies;
     std::vector<float> med(cand.size());
     for (size_t j = 0; j < cand.size(); ++j) {
       p->tuned[key] = cand[j];
       float t[3];
       for (int run = 0; run < 4; ++run) {
         const hipError_t e0 = hipEventRecord(ev.a, hs);
-        rc_status st = e0 == hipSuccess ? rc_process_batch(p, f, copies, stream)
+        rc_status st = e0 == hipSuccess ? rc_process_batch(p, f, n, stream)
                                         : fail(RC_EHIP, "tuning: %s", hipGetErrorString(e0));
+        if (st == RC_ENOTREADY && n > 1 && j == 0 && run == 0) {  // nothing was enqueued
+          g_err.clear();
+          --n;
+          --run;
+          continue;
+        }
         if (st == RC_OK) {
           hipError_t e = hipEventRecord(ev.b, hs);
           if (e == hipSuccess) e = hipEventSynchronize(ev.b);
           float ms = 0.f;
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.a, ev.b);
-          for (int k = 0; k < copies; ++k) {
+          for (int k = 0; k < n; ++k) {
             const rc_status rel = rc_frame_release(p, ids[k]);
             if (st == RC_OK) st = rel;
           }
           if (e != hipSuccess) st = fail(RC_EHIP, "tuning: %s", hipGetErrorString(e));
-          if (run > 0) t[run - 1] = ms / copies;
+          if (run > 0) t[run - 1] = ms / n;
         }
         if (st != RC_OK) {
           p->tuned.erase(key);
@@ -1720,11 +1730,12 @@ rc_status rc_plan_tune(void* plan, const rc_frame* frames, int32_t n_frames, voi
       std::sort(t, t + 3);
       med[j] = t[1];
     }
-    size_t best = 0;
-    for (size_t j = 1; j < cand.size(); ++j)
-      if (med[j] < 0.98f * med[0] && med[j] < med[best]) best = j;
+    const size_t i0 = (size_t)(std::find(cand.begin(), cand.end(), k0) - cand.begin());
+    size_t best = i0;
+    for (size_t j = 0; j < cand.size(); ++j)
+      if (med[j] < 0.98f * med[i0] && med[j] < med[best]) best = j;
     p->tuned[key] = cand[best];
-    out[c] = rc_tuning_entry{key[0], key[1], key[2], key[3], cand[best], k0, med[0], med[best]};
+    out[c] = rc_tuning_entry{key[0], key[1], key[2], key[3], cand[best], k0, med[i0], med[best]};
   }
   return RC_OK;
 }

@@ -1,9 +1,10 @@
 """Plan-time tuning of back-projection's chirp split, per size class
 (rc_plan_tune, rc_plan_set_tuning).  Checked here: the tuner returns one
-valid entry per class and installs it; a class given another split changes
-its image by rounding only, and plans given the same table agree bitwise; in
-a tuned plan a batch of mixed frames gives each frame's result alone,
-bitwise; an invalid table is refused and leaves the plan's table as it was."""
+valid entry per class and installs it, also under an HBM budget that holds
+fewer copies; a class given another split changes its image by rounding
+only, and plans given the same table agree bitwise; in a tuned plan a batch
+of mixed frames gives each frame's result alone, bitwise; an invalid table is
+refused and leaves the plan's table as it was."""
 import dataclasses
 
 import numpy as np
@@ -136,6 +137,26 @@ def test_tuned_plan_batch_equals_each_frame_alone(rc, torch, frames):
         for dev, fid, ref in ((da, 11, alone_a), (db, 12, alone_b), (db2, 13, alone_b)):
             assert np.array_equal(dev.img.cpu().numpy(), ref[0]), fid
             assert np.array_equal(outs[fid], ref[1]), fid
+
+
+def test_tuning_under_an_hbm_budget(rc, torch, frames):
+    """An arena of 2.5 frames: the tuner measures smaller batches and still
+    installs a valid table; the plan's results equal those of a slot plan
+    given the same table, bitwise."""
+    a, b = frames
+    da, db = _Dev(a, torch), _Dev(b, torch)
+    slots = _cfg(rc, frames)
+    probe = dataclasses.replace(slots, frame_memory=rc.RC_MEMORY_BUDGET, hbm_budget_bytes=1 << 40)
+    need = rc.frame_bytes(probe, da.desc(rc, 0))
+    with rc.Plan(dataclasses.replace(probe, hbm_budget_bytes=int(2.5 * need))) as plan:
+        table = plan.tune([da.desc(rc, 1), db.desc(rc, 2)])
+        assert len(table) == 2 and all(1 <= e["chirp_blocks"] <= 16 for e in table)
+        got = [_image(rc, plan, d, torch, 10 + k) for k, d in enumerate((da, db))]
+    with rc.Plan(slots) as ref_plan:
+        ref_plan.set_tuning(table)
+        ref = [_image(rc, ref_plan, d, torch, 10 + k) for k, d in enumerate((da, db))]
+    for g, r in zip(got, ref):
+        assert np.array_equal(g[0], r[0]) and np.array_equal(g[1], r[1])
 
 
 def test_invalid_table_is_refused_and_keeps_the_table(rc, torch, frames):
