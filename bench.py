@@ -40,6 +40,10 @@ METRIC = "radar frames/s and p50/p99 frame latency at 1 MI355X; % HBM roofline"
 VALU_LANE_OPS = 256 * 128 * 2.4e9
 HALF_SLOTS = 2.0
 TRANS_SLOTS = 4.0
+# the same classes' rates as the microbenchmarks measured them (midpoints of
+# the measured ranges: v_fma/v_fmac/v_add/v_mul 57-64, v_cvt/v_fract 36-37,
+# v_sqrt/v_sin 18-19 T lane-instructions/s); nominal full rate is 78.6 T
+MEASURED_LANE_RATES = {"full": 60.5e12, "half": 36.5e12, "trans": 18.5e12}
 HBM_PEAK_GBS = 8000.0
 PUBLISHED_FP32_TFLOPS = 157.3
 
@@ -65,6 +69,19 @@ def alg2_cost(chg: int):
     flops = 24.0 + 7.0 / chg
     slots = 11.0 + HALF_SLOTS + 3 * TRANS_SLOTS + (4.0 + TRANS_SLOTS) / chg
     return flops, slots
+
+
+def alg2_classes(chg: int):
+    """VALU instructions per back-projection term by rate class (full-rate
+    add/mul/FMA, half-rate conversion, transcendental), as alg2_cost counts
+    them: slots = full + HALF_SLOTS half + TRANS_SLOTS trans."""
+    return {"full": 11.0 + 4.0 / chg, "half": 1.0, "trans": 3.0 + 1.0 / chg}
+
+
+def measured_rate_ceiling(chg: int) -> float:
+    """Terms/s if every instruction class of the loop issued at its measured
+    rate (MEASURED_LANE_RATES), one class after another."""
+    return 1.0 / sum(n / MEASURED_LANE_RATES[k] for k, n in alg2_classes(chg).items())
 
 
 def _kernel_sources_digest() -> str:
@@ -1003,6 +1020,7 @@ def main(argv=None):
     bp_ms = float(stages[:, 2].mean())
     achieved = contrib / (bp_ms * 1e-3) * flops / 1e12
     peak = VALU_LANE_OPS / slots * flops / 1e12
+    measured_peak = measured_rate_ceiling(chg) * flops / 1e12
     range_bytes = float(M * CH) * (8 * cfg.n_samples + 8 * frame.n_bins)
     range_ms = float(stages[:, 0].mean())
     total = main_run["total_s"]
@@ -1066,6 +1084,11 @@ def main(argv=None):
             "published_fp32_peak": PUBLISHED_FP32_TFLOPS,
             "frac_of_published_fp32_peak": achieved / PUBLISHED_FP32_TFLOPS,
             "slots_per_term": slots,
+            "measured_rates_peak": measured_peak,
+            "frac_of_measured_rates": achieved / measured_peak,
+            "measured_rates_note": "the same loop's ceiling with each instruction class at the rate "
+                                   "microbenchmarks reach (full 60.5, half 36.5, transcendental 18.5 T "
+                                   "lane-instructions/s, against the nominal 78.6 T full rate)",
             "flops_per_term": flops,
             "traffic": measured_traffic(args.workload),
             "measured": "HIP events around each back-projection launch of the one-frame-in-flight run (the "

@@ -36,6 +36,21 @@ def test_chg4_ceiling():
     assert bench.VALU_LANE_OPS / slots == pytest.approx(2.9127e12, rel=1e-4)
 
 
+@pytest.mark.parametrize("chg", [1, 2, 4, 8, 16])
+def test_instruction_classes_match_the_slot_model(chg):
+    """The classes count the same instructions as the slot model, and at the
+    measured rates (each below its nominal one) the ceiling is lower."""
+    c = bench.alg2_classes(chg)
+    _, slots = bench.alg2_cost(chg)
+    assert c["full"] + bench.HALF_SLOTS * c["half"] + bench.TRANS_SLOTS * c["trans"] == pytest.approx(slots)
+    nominal = bench.VALU_LANE_OPS / slots
+    assert bench.measured_rate_ceiling(chg) < nominal
+    # chg 4: 12 full, 1 half, 3.25 transcendental instructions per term
+    if chg == 4:
+        t = 12 / 60.5e12 + 1 / 36.5e12 + 3.25 / 18.5e12
+        assert bench.measured_rate_ceiling(4) == pytest.approx(1 / t)
+
+
 def test_traffic_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
     """A counter summary counts only for the kernel sources whose hash it
     records: the same sources give its bytes, changed sources give none."""
