@@ -335,7 +335,10 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
     frame's device buffer on a copy stream; the frame's stream waits for that
     copy's event, so the copy of one frame overlaps the other frame's
     back-projection; latency then runs from the cube being ready in pinned
-    memory to the detections on the host."""
+    memory to the detections on the host.  upload="plan": the plan itself
+    takes the cube from pinned memory (an HBM-budget plan, rc_frame.data_host)
+    and copies it on its copy stream in chirp-block pieces, each block's
+    kernels waiting only for its own piece."""
     dev = torch.device("cuda:0")
     cfg = frame.cfg
     raw = torch.from_numpy(frame.raw).to(dev)
@@ -351,17 +354,25 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
         copy_stream = torch.cuda.Stream()
     else:
         raws = [raw] * n_streams
+    by_plan = upload == "plan"
     pc = rc.PlanConfig(radar=synth.RADAR, n_samples_max=cfg.n_samples, n_fft_max=frame.n_fft,
                        n_bins_max=frame.n_bins, n_chirps_max=cfg.n_chirps, n_channels_max=cfg.n_channels,
                        n_pix_max=n_pix, max_frames_in_flight=max(2, depth), max_detections=1 << 16,
                        precision=precision, doppler=doppler, stage_timing=True, **(plan_kw or {}))
+    if by_plan:  # an arena for the frames in flight plus one
+        probe = dataclasses.replace(pc, frame_memory=rc.RC_MEMORY_BUDGET, hbm_budget_bytes=1 << 40)
+        one = rc.frame_bytes(probe, rc.Plan.make_frame(
+            0, data=None, data_host=host, q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel, pixels=pix,
+            n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins, n_fft=frame.n_fft, fs=frame.fs,
+            n_samples=cfg.n_samples, height=cfg.height))
+        pc = dataclasses.replace(probe, hbm_budget_bytes=(max(2, depth) + 1) * one)
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
     lat, stages, n_det = [], [], 0
     last_dets = None
     with rc.Plan(pc) as plan:
         def submit(fid):
             k = fid % n_streams
-            if upload:  # the copy on its own stream, then the frame's kernels after it
+            if upload and not by_plan:  # the copy on its own stream, then the frame's kernels after it
                 # (buffer k was last read by frame fid - n_streams, which the
                 # loop below has already waited for)
                 with torch.cuda.stream(copy_stream):
@@ -369,10 +380,10 @@ def time_pipeline(rc, synth, torch, frame, pix_host, n_rows, n_cols, precision, 
                     ev = torch.cuda.Event()
                     ev.record(copy_stream)
                 streams[k].wait_event(ev)
-            fr = rc.Plan.make_frame(fid, data=raws[k], q_tx=frame.q_tx, q_rx=frame.q_rx, vel=frame.vel,
-                                    pixels=pix, n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins,
+            fr = rc.Plan.make_frame(fid, data=None if by_plan else raws[k], q_tx=frame.q_tx, q_rx=frame.q_rx,
+                                    vel=frame.vel, pixels=pix, n_rows=n_rows, n_cols=n_cols, n_bins=frame.n_bins,
                                     n_fft=frame.n_fft, fs=frame.fs, n_samples=cfg.n_samples, image_out=imgs[k],
-                                    height=cfg.height)
+                                    height=cfg.height, data_host=host if by_plan else None)
             plan.process([fr], streams[k])
 
         # the collector runs before the warm-up, not between it and the timed
@@ -1005,7 +1016,7 @@ def main(argv=None):
     up_run = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
                            rc.RC_PREC_FP32, args.steps, args.warmup, n_streams=args.streams, upload=True)
     up_lat = time_pipeline(rc, synth, torch, frame, frame.pix, frame.n_rows, frame.n_cols,
-                           rc.RC_PREC_FP32, 20, args.warmup, depth=1, upload=True)
+                           rc.RC_PREC_FP32, 20, args.warmup, depth=1, upload="plan")
     # per-stage device times (and the roofline) from the single-frame run: with
     # two frames on two streams, kernels of different frames overlap and a
     # launch's duration no longer measures the launch alone
@@ -1036,7 +1047,8 @@ def main(argv=None):
         "p50_ms": 1e3 * float(np.percentile(up_lat["lat"], 50)),
         "p99_ms": 1e3 * float(np.percentile(up_lat["lat"], 99)),
         "latency_note": "p50/p99: one frame in flight (20 frames), from its beat cube ready in pinned host "
-                        "memory (upload on the frame's stream) to its detections on the host; value and "
+                        "memory (handed to the plan, which copies it in chirp-block pieces, each block's "
+                        "kernels waiting for its own piece) to its detections on the host; value and "
                         "ms_per_step: frames streamed back to back, two in flight on "
                         f"{args.streams} stream(s), cubes resident in HBM; stages_ms: device stage times of "
                         "the resident one-frame run",

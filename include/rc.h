@@ -133,8 +133,12 @@ typedef enum rc_frame_memory {
    * RC_ENOMEM for a frame larger than the whole arena (it would never fit);
    * max_frames_in_flight still bounds the count.  A frame may then hand over
    * its input in pinned host memory (rc_frame.data_host): the plan copies it
-   * into the frame's share of the arena on the frame's stream before its
-   * kernels (the paper's pinned-memory Load, Sec. IV). */
+   * into the frame's share of the arena on a copy stream of its own, and the
+   * frame's kernels wait for the copy (the paper's pinned-memory Load,
+   * Sec. IV).  A batch of one frame whose back-projection splits its chirps
+   * into blocks is copied in those blocks' pieces, and each block's range
+   * compression and back-projection wait only for their own piece, so the
+   * later pieces' copies overlap the frame's own compute (same results). */
   RC_MEMORY_BUDGET = 1
 } rc_frame_memory;
 

@@ -366,9 +366,10 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(BpBatch b) {
   // (workgroup-uniform) results back to scalar registers so that the table
   // descriptors derived from them stay scalar
   const int local = xcd * a.chunk + (slot - a.slot_base);
-  if (local >= a.n_kb * a.n_tiles) return;
-  const int kb = __builtin_amdgcn_readfirstlane(local / a.n_tiles);
-  const int tile = local - kb * a.n_tiles;
+  if (local >= a.kb_count * a.n_tiles) return;
+  const int kb_local = __builtin_amdgcn_readfirstlane(local / a.n_tiles);
+  const int tile = local - kb_local * a.n_tiles;
+  const int kb = a.kb0 + kb_local;
   const int ty = __builtin_amdgcn_readfirstlane(tile / a.tiles_x);
   const int tx = tile - ty * a.tiles_x;
 
@@ -527,8 +528,8 @@ hipError_t launch_backproject(const BpBatch& b, hipStream_t s) {
         ((b.form == kBpExact || b.form == kBpDirect) && (!f.rowv || !f.grpv)) ||
         (b.form != kBpExact && b.form != kBpDirect && (!f.rowq || !f.grpq)) ||
         (b.sums == 3 && (!f.roww || (reinterpret_cast<uintptr_t>(f.roww) & 7))) || !f.out ||
-        f.n_kb < 1 || f.n_kb > f.n_chirps || f.tiles_x != tx || f.n_tiles != nt || f.slot_base != slots ||
-        f.chunk != (f.n_kb * nt + 7) / 8 ||
+        f.n_kb < 1 || f.n_kb > f.n_chirps || f.kb0 < 0 || f.kb_count < 1 || f.kb0 + f.kb_count > f.n_kb ||
+        f.tiles_x != tx || f.n_tiles != nt || f.slot_base != slots || f.chunk != (f.kb_count * nt + 7) / 8 ||
         (f.n_rows >= 8 && (f.n_rows + 15) / 16 > 0x7fffffff / 16) ||
         (int64_t)f.n_bins * 16 >= (int64_t)1 << 31 || (int64_t)f.n_chirps * f.n_ch >= (int64_t)1 << 31)
       return hipErrorInvalidValue;

@@ -155,9 +155,10 @@ struct BpFrame {
   int n_chirps, n_ch, n_bins;
   int n_rows, n_cols;
   int n_kb;               // chirp blocks
+  int kb0, kb_count;      // the blocks this launch evaluates: [kb0, kb0 + kb_count)
   int tiles_x, n_tiles;   // workgroup tiles per chirp block
-  // each XCD takes a contiguous chunk of ceil(n_kb n_tiles / 8) of the frame's
-  // items; slot_base is the frame's first per-XCD slot in the launch
+  // each XCD takes a contiguous chunk of ceil(kb_count n_tiles / 8) of the
+  // frame's items; slot_base is the frame's first per-XCD slot in the launch
   int chunk, slot_base;
   float a1;               // bins per wavelength of two-way path
   // bounding boxes of all TX / RX positions (wavelengths, local frame) and

@@ -181,6 +181,8 @@ struct Plan {
   // the batches before it; the batch's stream waits for them by an event
   hipStream_t copy_stream = nullptr;
   hipEvent_t copied = nullptr;
+  // a lone frame's input is copied in chirp-block pieces, one event each
+  hipEvent_t pieces[16] = {};
   // back-projection's chirp blocks per size class (n_rows, n_cols, n_chirps,
   // n_channels), installed by rc_plan_tune / rc_plan_set_tuning; classes not
   // listed take the rule of rc::bp_chirp_blocks
@@ -427,6 +429,8 @@ void free_plan(Plan* p) {
   if (p->copy_stream) (void)hipStreamSynchronize(p->copy_stream);
   if (p->arena) (void)hipFree(p->arena);
   if (p->copied) (void)hipEventDestroy(p->copied);
+  for (hipEvent_t& e : p->pieces)
+    if (e) (void)hipEventDestroy(e);
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   for (Sensor& s : p->sensors)
     if (s.done) (void)hipEventDestroy(s.done);
@@ -789,6 +793,8 @@ rc_status prepare_frame(Plan* p, Slot& s, const rc_frame& f, const Slide* sl, hi
   ba.n_rows = f.n_rows;
   ba.n_cols = f.n_cols;
   ba.n_kb = n_kb;
+  ba.kb0 = 0;
+  ba.kb_count = n_kb;
   rc::bp_tiles(f.n_rows, f.n_cols, &ba.tiles_x, &ba.n_tiles);
   ba.a1 = (float)(a1 * lam);
   ba.tx_lo_x = tlx; ba.tx_lo_y = tly; ba.tx_hi_x = thx; ba.tx_hi_y = thy;
@@ -1043,7 +1049,7 @@ rc_status rc_process_frame_static(const rc_plan_desc* desc, const rc_frame* fram
              : shape.d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
              : split_phase(shape.d) ? rc::kBpSplit : rc::kBpPlain;
     rc::BpFrame bf = prep.bf;
-    bf.chunk = (bf.n_kb * bf.n_tiles + 7) / 8;
+    bf.chunk = (bf.kb_count * bf.n_tiles + 7) / 8;
     bf.slot_base = 0;
     b.f[b.n_frames++] = bf;
     b.n_slots = bf.chunk;
@@ -1182,6 +1188,8 @@ rc_status rc_plan_create(const rc_plan_desc* desc, void** out) {
     p->free_list.emplace(0, p->arena_bytes);
     e = hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->copied, hipEventDisableTiming);
+    for (hipEvent_t& ev : p->pieces)
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e != hipSuccess) {
       free_plan(p);
       return fail(RC_EHIP, "copy stream: %s", hipGetErrorString(e));
@@ -1355,13 +1363,37 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   // batch's stream waits for before its kernels.  A share is taken only from
   // ranges whose frames have completed, so no earlier work on any stream
   // still reads it.
+  // A lone frame whose back-projection has several chirp blocks is copied in
+  // pieces of those blocks' rows: each block's range compression and
+  // back-projection wait only for its own piece, so all but the first piece's
+  // copy overlap the frame's own compute (the results are those of the whole
+  // launches: the same kernels over the same rows and blocks).
+  const bool piped = n_frames == 1 && frames[0].data_host && prep[0].raw_in && !prep[0].recheck &&
+                     slide[0].sensor < 0 && prep[0].bf.n_kb > 1 && prep[0].bf.n_kb <= 16 && p->pieces[0];
+  auto block_rows = [&](int k, int64_t* r0, int64_t* r1) {  // the kernel's split of the chirps
+    const rc::BpFrame& b = prep[0].bf;
+    *r0 = (int64_t)(((int64_t)k * b.n_chirps) / b.n_kb) * b.n_ch;
+    *r1 = (int64_t)(((int64_t)(k + 1) * b.n_chirps) / b.n_kb) * b.n_ch;
+  };
   bool any_host = false;
-  for (int i = 0; i < n_frames; ++i)
-    if (frames[i].data_host) {
-      RC_BATCH(hipMemcpyAsync(slot[i]->input, frames[i].data_host, fsz[i].input, hipMemcpyHostToDevice,
-                              p->copy_stream));
-      any_host = true;
+  if (piped) {
+    const size_t row_bytes = (size_t)frames[0].n_samples * sizeof(float2);
+    for (int k = 0; k < prep[0].bf.n_kb; ++k) {
+      int64_t r0, r1;
+      block_rows(k, &r0, &r1);
+      RC_BATCH(hipMemcpyAsync(static_cast<char*>(slot[0]->input) + r0 * row_bytes,
+                              static_cast<const char*>(frames[0].data_host) + r0 * row_bytes,
+                              (size_t)(r1 - r0) * row_bytes, hipMemcpyHostToDevice, p->copy_stream));
+      RC_BATCH(hipEventRecord(p->pieces[k], p->copy_stream));
     }
+  } else {
+    for (int i = 0; i < n_frames; ++i)
+      if (frames[i].data_host) {
+        RC_BATCH(hipMemcpyAsync(slot[i]->input, frames[i].data_host, fsz[i].input, hipMemcpyHostToDevice,
+                                p->copy_stream));
+        any_host = true;
+      }
+  }
   if (any_host) {
     RC_BATCH(hipEventRecord(p->copied, p->copy_stream));
     RC_BATCH(hipStreamWaitEvent(st, p->copied, 0));
@@ -1381,7 +1413,7 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   {
     std::vector<char> done(n_frames, 0);
     for (int i = 0; i < n_frames; ++i) {
-      if (done[i] || !prep[i].raw_in) continue;
+      if (done[i] || !prep[i].raw_in || piped) continue;
       rc::RangeMulti m;
       for (int j = i; j < n_frames && m.n_frames < rc::RangeMulti::kMax; ++j)
         if (!done[j] && prep[j].raw_in && prep[j].ra.log2n == prep[i].ra.log2n) {
@@ -1427,6 +1459,40 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
   };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return item_cost(x) > item_cost(y); });
   std::vector<char> done(n_frames, 0);
+  if (piped) {
+    // per chirp block: wait for its piece, then its range compression and
+    // its back-projection
+    for (int k = 0; k < prep[0].bf.n_kb; ++k) {
+      int64_t r0, r1;
+      block_rows(k, &r0, &r1);
+      RC_BATCH(hipStreamWaitEvent(st, p->pieces[k], 0));
+      rc::RangeMulti m;
+      rc::RangeArgs ra = prep[0].ra;
+      ra.raw += r0 * ra.n_s;
+      ra.w_sar += r0 / ra.n_ch;
+      ra.pairs += r0 * ra.n_bins;
+      if (ra.spectrum) ra.spectrum += r0 * ra.n_bins;
+      ra.rows = r1 - r0;
+      m.f[m.n_frames++] = ra;
+      RC_BATCH(mfma_spectrum(p->d) ? rc::launch_range_mfma(m, p->d.precision == RC_PREC_BF16, st)
+                                   : rc::launch_range_compress(m, st));
+      rc::BpBatch b{};
+      b.chg = prep[0].chg;
+      b.sums = prep[0].sums;
+      b.form = p->d.doppler == RC_DOPPLER_EXACT_DIRECT ? rc::kBpDirect
+               : p->d.doppler == RC_DOPPLER_EXACT ? rc::kBpExact
+               : split_phase(p->d) ? rc::kBpSplit : rc::kBpPlain;
+      rc::BpFrame bf = prep[0].bf;
+      bf.kb0 = k;
+      bf.kb_count = 1;
+      bf.chunk = (bf.n_tiles + 7) / 8;
+      bf.slot_base = 0;
+      b.f[b.n_frames++] = bf;
+      b.n_slots = bf.chunk;
+      RC_BATCH(rc::launch_backproject(b, st));
+    }
+    done[0] = 1;
+  }
   for (int oi = 0; oi < n_frames; ++oi) {
     const int i = order[oi];
     if (done[i]) continue;
@@ -1440,7 +1506,7 @@ rc_status rc_process_batch(void* plan, const rc_frame* frames, int32_t n_frames,
       const int j = order[oj];
       if (done[j] || prep[j].chg != prep[i].chg || prep[j].sums != prep[i].sums) continue;
       rc::BpFrame fj = prep[j].bf;
-      fj.chunk = (fj.n_kb * fj.n_tiles + 7) / 8;
+      fj.chunk = (fj.kb_count * fj.n_tiles + 7) / 8;
       fj.slot_base = b.n_slots;
       b.f[b.n_frames++] = fj;
       b.n_slots += fj.chunk;
