@@ -2,7 +2,8 @@
 plan's arena the bytes its own sizes need and gives them back at release.
 Checked here: the same frames give bitwise the same image and detections as a
 plan of fixed slots, with the input handed over on the device or in pinned
-host memory; a batch that does not fit what is free is refused without
+host memory (a lone frame's copied in chirp-block pieces, in every precision
+form); a batch that does not fit what is free is refused without
 enqueuing anything and is admitted once a frame is released; small frames
 share a budget that holds only one frame of the plan's limits; the serving
 loop admits by bytes; a continuous-SAR stream gives the slot plan's
@@ -93,6 +94,28 @@ def test_budget_plan_equals_slot_plan(rc, torch):
                 plan.release(fid)
                 assert np.array_equal(img, ref[k][0]), (host, k)
                 assert np.array_equal(dets, ref[k][1]), (host, k)
+
+
+@pytest.mark.parametrize("precision", ["RC_PREC_FP32_SPLIT", "RC_PREC_FP16", "RC_PREC_BF16"])
+def test_host_input_in_chirp_block_pieces_equals_slot_plan(rc, torch, precision):
+    """A lone frame handed over in pinned memory is copied in its chirp
+    blocks' pieces, each block's range compression (on the FP32 FFT or the
+    matrix cores) and back-projection waiting only for its piece: bitwise the
+    image and detections of the whole launches in a slot plan."""
+    big, _ = _frames()
+    fr = synth.make_frame(dataclasses.replace(big.cfg, name="pieces", n_samples=256, seed=903))
+    x = _Inputs(fr, torch)
+    base = SC.plan_config(rc, [fr], max_frames_in_flight=2, precision=getattr(rc, precision))
+    with rc.Plan(base) as plan:
+        plan.process([x.desc(rc, 1)])
+        ref = _result(rc, plan, torch, 1, fr.n_rows * fr.n_cols)
+    budget = dataclasses.replace(base, frame_memory=rc.RC_MEMORY_BUDGET, hbm_budget_bytes=rc.slot_bytes(base) * 3)
+    with rc.Plan(budget) as plan:
+        for fid in (2, 3):
+            plan.process([x.desc(rc, fid, host=True)])
+            got = _result(rc, plan, torch, fid, fr.n_rows * fr.n_cols)
+            plan.release(fid)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), fid
 
 
 def test_budget_admission_waits_for_release(rc, torch):
