@@ -367,8 +367,11 @@ rc_status rc_image(void* plan, int64_t frame_id, void* dst, int64_t cap_pixels,
 /* Blocks until the frame completes; ms4 (host, float[4]) receives the device
  * time in milliseconds of range compression, the per-frame tables,
  * back-projection and detection (CFAR + compaction), measured with HIP events
- * recorded on the frame's stream around each stage.  RC_EINVAL if the plan
- * was created with stage_timing = 0. */
+ * recorded on the frame's stream around each stage.  A lone frame copied from
+ * pinned memory in chirp-block pieces (RC_MEMORY_BUDGET) runs range
+ * compression block by block inside back-projection: its range time reads 0
+ * and its back-projection time includes range compression and the waits for
+ * its pieces.  RC_EINVAL if the plan was created with stage_timing = 0. */
 rc_status rc_stage_times(void* plan, int64_t frame_id, float* ms4);
 
 /* Waits for the frame and returns its slot to the free pool. */
