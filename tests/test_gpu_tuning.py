@@ -179,6 +179,16 @@ def test_invalid_table_is_refused_and_keeps_the_table(rc, torch, frames):
         with pytest.raises(rc.RcError) as ei:
             plan.tune([fr])
         assert ei.value.status == rc.RC_EINVAL
+        # an output table shorter than the classes: RC_ETRUNC with the class
+        # count, nothing measured or installed; no frames: no classes
+        import ctypes as C
+        two = (rc.rc_frame * 2)(da.desc(rc, 6), _Dev(b, torch).desc(rc, 7))
+        one = (rc.rc_tuning_entry * 1)()
+        n = C.c_int32()
+        assert rc.lib.rc_plan_tune(plan.handle, two, 2, None, one, 1, C.byref(n)) == rc.RC_ETRUNC
+        assert n.value == 2
+        assert rc.lib.rc_plan_tune(plan.handle, two, 0, None, one, 0, C.byref(n)) == rc.RC_OK
+        assert n.value == 0
         plan.set_tuning([])
         cleared = _image(rc, plan, da, torch, 3)
     with rc.Plan(_cfg(rc, frames)) as fresh:
